@@ -1,0 +1,579 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses a printed value
+(tests/golden/paper_values.json), a closed form typed in independently, a brute
+force computation from a definition, an identity, or an independent solver.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cosmology as cos
+from oracle import spectral as sp
+from oracle import field as fld
+from oracle import newton, pm, power, adjoint
+from paper_0906_4548_amd import inputs
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+OM0 = GOLDEN["omega_m0_default"]["value"]
+
+
+def params(a=0.5, **kw):
+    return fld.SolveParams.from_cosmology(OM0, a, **kw)
+
+
+# ---------------------------------------------------------------- background and coefficients
+
+def test_background_satisfies_friedmann():
+    # Eq. DGPFriedmann in H0 units: E^2 = (1 - Om0) E + Om0 a^-3, with r_c H0 = 1/(1-Om0)
+    for a in (0.04, 0.1, 0.5, 1.0):
+        e = cos.hubble_E(OM0, a)
+        assert abs(e * e - ((1 - OM0) * e + OM0 / a ** 3)) < 1e-12 * e * e
+    assert abs(cos.hubble_E(OM0, 1.0) - 1.0) < 1e-15
+
+
+def test_coefficient_identities():
+    # closed forms typed from Sec. II; q from its definition a a''/a'^2 computed by finite differences of E
+    c = cos.coefficients(OM0, 0.5)
+    eta = c.eta
+    assert abs(c.alpha - 3 * (2 * eta ** 2 - 2 * eta + 1) / (eta * (2 * eta - 1))) < 1e-14
+    assert abs(c.beta - (2 * eta ** 2 - 2 * eta - 1) / (eta * (2 * eta - 1))) < 1e-14
+    # Omega_m(a) = (eta-1)/eta equals Om0 a^-3 / E^2 (matter fraction of the expansion rate)
+    assert abs((eta - 1) / eta - OM0 / (0.5 ** 3 * c.E ** 2)) < 1e-13
+    # q = a'' a / a'^2 = 1 + dlnH/dlna; dlnE/dlna by central differences
+    h = 1e-5
+    dl = (math.log(cos.hubble_E(OM0, 0.5 * math.exp(h))) - math.log(cos.hubble_E(OM0, 0.5 * math.exp(-h)))) / (2 * h)
+    assert abs(c.q - (1 + dl)) < 1e-8
+
+
+def test_w_zero_discriminant_z24_printed():
+    g = GOLDEN["w_zero_discriminant_z24"]
+    w = cos.w_zero_discriminant(g["omega_m0"], 1.0 / (1.0 + g["z"]))
+    assert round(w, g["digits"]) == g["value"]
+
+
+def test_discriminant_sign_vs_redshift_fig2():
+    g0 = GOLDEN["discriminant_w0_negative_above_z"]
+    om = g0["omega_m0"]
+    for z in (1.2, 2.0, 5.0, 10.0, 24.0, 49.0):
+        assert cos.discriminant_c_free(om, 1 / (1 + z), 0.0) < 0.0
+    for z in (0.0, 0.3, 0.6):
+        assert cos.discriminant_c_free(om, 1 / (1 + z), 0.0) > 0.0
+    # the sign change sits near z = 1 (within the resolution of the printed statement)
+    zs = np.linspace(0.5, 1.5, 1001)
+    vals = np.array([cos.discriminant_c_free(om, 1 / (1 + z), 0.0) for z in zs])
+    zc = zs[np.argmax(vals < 0)]
+    assert 0.8 < zc < 1.2
+    for z in np.linspace(0.0, 100.0, 401):
+        assert cos.discriminant_c_free(om, 1 / (1 + z), 1.0 / 3.0) > 0.0
+
+
+def test_det2d_positive_in_voids():
+    for om in (0.2, 0.27, 0.3):
+        for z in np.linspace(0.0, 100.0, 201):
+            assert cos.monge_ampere_det_2d(om, 1 / (1 + z), -1.0) > 0.0
+
+
+# ---------------------------------------------------------------- FFT and multipliers
+
+def test_fft_matches_bruteforce_dft_8():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((8, 8, 8))
+    full = sp.dft3_bruteforce(x)
+    half = sp.fft3(x)
+    assert np.max(np.abs(half - full[:, :, :5])) < 1e-12 * np.max(np.abs(full))
+    back = sp.ifft3(half, 8)
+    assert np.max(np.abs(back - x)) < 1e-14
+
+
+def test_parseval():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((16, 16, 16))
+    xk = sp.fft3(x)
+    mult = np.ones(xk.shape)
+    mult[:, :, 1:8] = 2.0
+    assert abs(np.sum(mult * np.abs(xk) ** 2) / 16 ** 3 - np.sum(x * x)) < 1e-10 * np.sum(x * x)
+
+
+def test_trace_identity():
+    n, box = 16, 32.0
+    u = inputs.gaussian_field(n, box, 3)
+    h, _ = fld.hessian_fields(u, box, params())
+    tr = h[0, 0] + h[1, 1] + h[2, 2]
+    assert np.max(np.abs(tr - (u - u.mean()))) < 1e-13 * np.max(np.abs(u))
+
+
+def _band_limited(n, box, seed):
+    """Random real field with every Nyquist-index mode removed."""
+    u = inputs.gaussian_field(n, box, seed)
+    uk = sp.fft3(u)
+    m0, m1, m2 = sp.mode_numbers(n)
+    keep = (np.abs(m0) < n // 2) & (np.abs(m1) < n // 2) & (m2 < n // 2)
+    return sp.ifft3(np.where(keep, uk, 0.0), n)
+
+
+def test_nonlinear_kernel_matches_eq_nlfourier_bruteforce():
+    """FFT(u^2 - sum h^2)(k) = N^-3 sum_{k1+k2=k mod N} (1 - mu^2) u(k1) u(k2)  (Eq. NLFourier).
+
+    The right side is evaluated from its definition: a double sum over all mode
+    pairs with mu the cosine between the (signed) wavevectors.  This pins the
+    Hessian multipliers, the pair weights of sum h_ij^2 and the transforms.
+    """
+    n, box = 8, 8.0
+    u = _band_limited(n, box, 5)
+    h, _ = fld.hessian_fields(u, box, params())
+    lhs = np.fft.fftn(u * u - fld.hessian_square_sum(h))
+    uk = np.fft.fftn(u)
+    m = np.fft.fftfreq(n, 1.0 / n)
+    vecs = np.array(np.meshgrid(m, m, m, indexing='ij')).reshape(3, -1).T
+    idx = np.array(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing='ij')).reshape(3, -1).T
+    uflat = uk.reshape(-1)
+    norm = np.linalg.norm(vecs, axis=1)
+    rhs = np.zeros((n, n, n), dtype=complex)
+    for a in range(n ** 3):
+        if norm[a] == 0 or abs(uflat[a]) < 1e-300:
+            continue
+        dots = vecs @ vecs[a]
+        with np.errstate(invalid='ignore', divide='ignore'):
+            mu2 = np.where(norm > 0, dots ** 2 / (norm ** 2 * norm[a] ** 2), 1.0)
+        kern = np.where(norm > 0, 1.0 - mu2, 0.0)
+        tgt = (idx + idx[a]) % n
+        np.add.at(rhs, (tgt[:, 0], tgt[:, 1], tgt[:, 2]), kern * uflat[a] * uflat)
+    rhs /= n ** 3
+    assert np.max(np.abs(lhs - rhs)) < 1e-11 * np.max(np.abs(rhs))
+
+
+def test_nyquist_mode_derivatives():
+    """The symmetric trigonometric interpolant of a Nyquist-index mode cos(pi j) is cos(pi x/h),
+    whose first derivative vanishes at every node: the spectral gradient of such a mode and its
+    mixed second derivatives are exactly 0, while its pure second derivative is -(pi/h)^2 times it."""
+    n, box = 16, 32.0
+    h = box / n
+    x = np.arange(n) * h
+    ky = 2 * np.pi * 3 / box
+    f = np.cos(np.pi * x / h)[:, None, None] * np.cos(ky * x)[None, :, None] * np.ones((n, n, n))
+    fk = sp.fft3(f)
+    for i in range(3):
+        gi = sp.ifft3(sp.gradient_multiplier(i, n, box) * fk, n)
+        if i == 0:
+            assert np.max(np.abs(gi)) < 1e-12
+    hxy = sp.ifft3(sp.hessian_multiplier(0, 1, n, box) * fk, n)
+    assert np.max(np.abs(hxy)) < 1e-12
+    # k_x^2/k^2 u with u = lap f = -((pi/h)^2 + ky^2) f
+    kx = np.pi / h
+    hxx = sp.ifft3(sp.hessian_multiplier(0, 0, n, box) * fk, n)
+    assert np.max(np.abs(hxx - kx ** 2 / (kx ** 2 + ky ** 2) * f)) < 1e-12
+
+
+def test_divergence_identity_and_p2_decomposition():
+    # <u^2 - sum h^2> = 0 (the (1 - mu^2) kernel vanishes at k = 0); Eqs. MonQuad / implementP2
+    n, box = 16, 32.0
+    u = _band_limited(n, box, 6)
+    h, _ = fld.hessian_fields(u, box, params())
+    sh2 = fld.hessian_square_sum(h)
+    assert abs(np.mean(u * u - sh2)) < 1e-13 * np.mean(u * u)
+    p2 = 1.5 * sh2 - 0.5 * u * u
+    assert np.max(np.abs((u * u - sh2) - ((2 / 3) * u * u - (2 / 3) * p2))) < 1e-13 * np.max(u * u)
+
+
+# ---------------------------------------------------------------- solver special cases
+
+def test_planar_wave_closed_form():
+    """delta depending on one coordinate: (1 - mu^2) = 0 for collinear modes, so the
+    solution is the linear closed form u = A (1 - beta/kbar) delta / (alpha - gamma/kbar)."""
+    n, box = 16, 64.0
+    prm = params(tol=1e-13, max_iter=50)
+    x = np.arange(n) * box / n
+    eps_amp = 0.8
+    m0 = 3
+    k0 = 2 * np.pi * m0 / box
+    delta = eps_amp * np.cos(k0 * x)[None, :, None] * np.ones((n, n, n))
+    kb = prm.kappa * k0
+    u_exact = prm.A * (1 - prm.beta / kb) / (prm.alpha - prm.gamma / kb) * delta
+    # from the linear guess the planar solution is reached with zero updates at any lam;
+    # from u = 0 the relaxation converges to it when no bad points arise (moderate lam)
+    for lam, init in ((1.0, fld.INIT_LINEAR), (50.0, fld.INIT_LINEAR), (1.0, fld.INIT_ZERO)):
+        if True:
+            p = prm.with_(lam=lam, init=init)
+            u, info = fld.solve(delta, box, p)
+            assert info.status == fld.STATUS_OK
+            assert np.max(np.abs(u - u_exact)) < 1e-12 * np.max(np.abs(u_exact))
+            if init == fld.INIT_LINEAR:
+                assert info.iters == 0
+
+
+def test_first_w13_update_is_spherical_poisson():
+    """One w = 1/3 update from u = 0, nonlocal terms off: inserting u_1 into Eq. FullDGP1
+    gives the modified Poisson source of Eq. SphPoi (spherical approximation)."""
+    n, box = 16, 32.0
+    c = cos.coefficients(OM0, 0.5)
+    prm = params(nonlocal_terms=False, lam=1.0)
+    delta = inputs.lognormal_delta(n, box, 0.8, 7)
+    d0 = delta - delta.mean()
+    u1 = fld.spherical_first_update(delta, box, prm)
+    lap_phi_from_u = 1.5 * (c.eta - 1) / c.eta * d0 - u1 / (2 * c.eta)
+    sphpoi = (1.5 * (c.eta - 1) / c.eta * d0
+              - (1 / (2 * c.eta)) * (3 * c.alpha / 4)
+              * (np.sqrt(1 + 8 / c.alpha ** 2 * (c.eta - 1) / c.eta * d0) - 1))
+    assert np.max(np.abs(lap_phi_from_u - sphpoi)) < 1e-13
+
+
+def test_oh_symmetric_centre():
+    """A delta invariant under the cube group about a grid point has an isotropic Hessian
+    there: h_ij = ((u - <u>)/3) delta_ij, so Eq. FullDGP2 at that point reduces to
+    lam (u^2 - (u - <u>)^2/3) + alpha u + gamma Nf = S (Eq. FullDGP2sph's local form)."""
+    n, box = 24, 48.0
+    c0 = 7
+    g = np.arange(n)
+    d = np.minimum(np.abs(g - c0), n - np.abs(g - c0)) * box / n
+    r2 = d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2
+    delta = 3.0 * np.exp(-r2 / (2 * 4.0 ** 2)) - 0.2 * np.exp(-r2 / (2 * 9.0 ** 2))
+    prm = params(tol=1e-13, max_iter=200, lam=0.3)
+    u, info = fld.solve(delta, box, prm)
+    assert info.status == fld.STATUS_OK
+    h, nf = fld.hessian_fields(u, box, prm)
+    s, _, _ = fld.source(delta, box, prm)
+    uc, ub = u[c0, c0, c0], u.mean()
+    for p in fld.PAIRS:
+        want = (uc - ub) / 3 if p[0] == p[1] else 0.0
+        assert abs(h[p][c0, c0, c0] - want) < 1e-12 * abs(uc)
+    lhs = prm.lam * (uc * uc - (uc - ub) ** 2 / 3) + prm.alpha * uc + prm.gamma * nf[c0, c0, c0]
+    assert abs(lhs - s[c0, c0, c0]) < 1e-11 * abs(s[c0, c0, c0])
+
+
+def test_spherical_tophat_radial_solution():
+    """Smooth spherical overdensity, nonlocal terms off.  For radial C(r) the quadratic
+    terms are 4 C'' C'/r + 2 (C'/r)^2 = (2/r^2)(r C'^2)', so Eq. FullDGP2 integrates to
+    2 lam r g^2 + alpha r^2 g = A m(r), g = C', m = int_0^r delta s^2 ds, i.e.
+    g/r = [-alpha + sqrt(alpha^2 + (8/3) lam A deltabar(<r))] / (4 lam).
+    The periodic mesh and finite resolution only allow discretisation-level agreement."""
+    n, box = 64, 64.0
+    prm = params(nonlocal_terms=False, tol=1e-12, max_iter=300)
+    cc = n // 2
+    g = (np.arange(n) - cc) * box / n
+    r = np.sqrt(g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2)
+    sig = 3.0
+    d_prof = 2.0 * np.exp(-r ** 2 / (2 * sig ** 2))
+    lam = 1.0
+    u, info = fld.solve(d_prof, box, prm.with_(lam=lam))
+    assert info.status == fld.STATUS_OK
+    # analytic profile of the mean-removed delta (the mesh solver removes the sample mean)
+    dbar_bg = d_prof.mean()
+    rr = np.linspace(1e-6, 12.0, 4001)
+    m_prof = 2.0 * sig ** 3 * (np.sqrt(np.pi / 2) * __import__('scipy').special.erf(rr / (np.sqrt(2) * sig))
+                                - (rr / sig) * np.exp(-rr ** 2 / (2 * sig ** 2)))
+    m = m_prof - dbar_bg * rr ** 3 / 3
+    dbar = 3 * m / rr ** 3
+    gr = (-prm.alpha + np.sqrt(prm.alpha ** 2 + (8 / 3) * lam * prm.A * dbar)) / (4 * lam)   # g/r
+    gfun = gr * rr
+    u_an = np.gradient(rr ** 2 * gfun, rr) / rr ** 2
+    sel = (r > 0.5) & (r < 8.0)
+    u_an_at = np.interp(r[sel], rr, u_an)
+    err = np.max(np.abs(u[sel] - u_an_at)) / np.max(np.abs(u_an_at))
+    assert err < 5e-3
+    # and the nonlinear solution differs from the linear one by far more than that
+    s, sk, _ = fld.source(d_prof, box, prm)
+    ul = fld.linear_solution(sk, box, prm)
+    assert np.max(np.abs(ul[sel] - u_an_at)) / np.max(np.abs(u_an_at)) > 0.1
+
+
+def test_geff_is_the_linear_limit():
+    """Linear u inserted in Eq. FullDGP1 gives phi/phi_GR = G_eff/G of Eq. Geff up to O(1/kbar^2)."""
+    n = 16
+    a = 0.5
+    c = cos.coefficients(OM0, a)
+    prm = params(a=a)
+    errs = []
+    for box in (20000.0, 2000.0, 200.0):
+        m0 = 1
+        x = np.arange(n) * box / n
+        delta = 0.01 * np.cos(2 * np.pi * m0 * x / box)[:, None, None] * np.ones((n, n, n))
+        phik_l = pm.phi_spectrum(delta, None, box, prm, OM0, a, pm.FORCE_LDGP)
+        phik_g = pm.phi_spectrum(delta, None, box, prm, OM0, a, pm.FORCE_GRH)
+        ratio = (phik_l[m0, 0, 0] / phik_g[m0, 0, 0]).real
+        k = 2 * np.pi * m0 / box
+        kb = c.kappa * k
+        errs.append((kb, abs(ratio - cos.geff_ratio(OM0, a, k))))
+    for kb, e in errs:
+        assert e * kb ** 2 < 1.0
+    assert errs[-1][1] < errs[0][1] * 1e-3
+
+
+# ---------------------------------------------------------------- fixed point against independent solvers
+
+def _c1_like(n, box, sigma, seed, rnl, **kw):
+    prm = params(**kw)
+    delta = inputs.lognormal_delta(n, box, sigma, seed)
+    _, sk, _ = fld.source(delta, box, prm)
+    ul = fld.linear_solution(sk, box, prm)
+    return delta, prm.with_(lam=rnl * prm.alpha / np.max(np.abs(ul))), ul
+
+
+def test_picard_fixed_point_equals_newton_krylov():
+    delta, prm, _ = _c1_like(16, 32.0, 1.0, 11, 3.0, tol=1e-13, max_iter=200)
+    u, info = fld.solve(delta, 32.0, prm)
+    assert info.status == fld.STATUS_OK
+    un, hist = newton.newton_krylov(delta, 32.0, prm, tol=1e-14)
+    assert hist[-1] < 1e-13
+    assert np.max(np.abs(u - un)) < 1e-11 * np.max(np.abs(un))
+
+
+def test_picard_fixed_point_equals_dense_newton_8():
+    delta, prm, _ = _c1_like(8, 16.0, 1.0, 12, 3.0, tol=1e-14, max_iter=200)
+    u, info = fld.solve(delta, 16.0, prm)
+    un, hist = newton.dense_newton(delta, 16.0, prm)
+    assert hist[-1] < 1e-14
+    assert np.max(np.abs(u - un)) < 1e-12 * np.max(np.abs(un))
+
+
+def test_fixed_point_is_invariant_under_w():
+    # Sec. III C: under the correct C the result is invariant under w
+    delta, prm, _ = _c1_like(16, 32.0, 1.0, 13, 3.0, tol=1e-13, max_iter=300)
+    u3, i3 = fld.solve(delta, 32.0, prm.with_(w=1 / 3))
+    u5, i5 = fld.solve(delta, 32.0, prm.with_(w=0.5))
+    uz, iz = fld.solve(delta, 32.0, prm.with_(w=cos.w_zero_discriminant(OM0, 0.5) % 1.0 if False else 0.25))
+    for uu in (u5, uz):
+        assert np.max(np.abs(uu - u3)) < 1e-11 * np.max(np.abs(u3))
+
+
+def test_linear_regime_is_linear():
+    delta, prm, ul = _c1_like(16, 32.0, 1.0, 14, 0.01, tol=1e-12)
+    u, info = fld.solve(delta, 32.0, prm)
+    dev = np.max(np.abs(u - ul)) / np.max(np.abs(ul))
+    assert 1e-4 < dev < 0.05
+
+
+def test_converged_solution_is_elliptic_everywhere():
+    """Appendix (Ellipticity): dF/d(h_ij) = (2 lam u + alpha) I - 2 lam h has eigenvalues of
+    one sign at every point of the converged w = 1/3 solution."""
+    delta, prm, _ = _c1_like(32, 64.0, 1.0, 1, 3.0, tol=1e-10)
+    u, info = fld.solve(delta, 64.0, prm)
+    h, _ = fld.hessian_fields(u, 64.0, prm)
+    mat = np.empty(u.shape + (3, 3))
+    for (i, j) in fld.PAIRS:
+        mat[..., i, j] = -2 * prm.lam * h[i, j]
+        mat[..., j, i] = -2 * prm.lam * h[i, j]
+    for i in range(3):
+        mat[..., i, i] += 2 * prm.lam * u + prm.alpha
+    ev = np.linalg.eigvalsh(mat.reshape(-1, 3, 3))
+    assert np.all(ev > 0) or np.all(ev < 0)
+
+
+def test_bad_point_takes_the_vertex():
+    """Where Delta < 0 the paper sets the discriminant to zero in Eq. nabla^2Cwpara, giving
+    u = -alpha / (2 (1 - w)) (times 1/lam with the nonlinear coefficient)."""
+    n, box = 8, 16.0
+    prm = params(nonlocal_terms=False, lam=2.0, w=0.5)
+    delta = np.zeros((n, n, n))
+    delta[1, 2, 3] = -0.999 * n ** 3 / 2
+    delta[5, 5, 5] = 0.999 * n ** 3 / 2
+    s, _, _ = fld.source(delta, box, prm)
+    zero = np.zeros_like(s)
+    u1, nbad = fld.picard_update(zero, {p: zero for p in fld.PAIRS}, zero, s, prm)
+    disc = prm.alpha ** 2 + 4 * (1 - prm.w) * prm.lam * s
+    assert nbad == int(np.sum(disc < 0)) and nbad > 0
+    assert np.all(u1[disc < 0] == -prm.alpha / (2 * (1 - prm.w) * prm.lam))
+    good = disc >= 0
+    assert np.allclose(u1[good], (-prm.alpha + np.sqrt(disc[good])) / (2 * (1 - prm.w) * prm.lam), rtol=1e-12, atol=1e-14)
+
+
+def test_bad_points_w0_stop_at_minimum():
+    """w = 0 at z = 4 (where the C-free part of Eq. Discweq0 is negative in voids) on a
+    log-normal field with deep voids: bad points appear, the residual stalls above 1 %
+    and the iteration stops at its minimum, returning that iterate; w = 1/3 converges
+    (Sec. III C, Figs. 2-4 discussion)."""
+    box = 32.0
+    prm = fld.SolveParams.from_cosmology(OM0, 0.2, tol=1e-12, max_iter=60, lam=1.0)
+    delta = inputs.lognormal_delta(16, box, 1.5, 21)
+    u, info = fld.solve(delta, box, prm.with_(w=0.0, init=fld.INIT_ZERO))
+    assert max(info.bad_history) > 0
+    assert info.status == fld.STATUS_BAD_POINTS
+    assert info.resid == min(info.history) and info.resid > 1e-2
+    u3, i3 = fld.solve(delta, box, prm.with_(w=1 / 3, init=fld.INIT_ZERO))
+    assert i3.status == fld.STATUS_OK and i3.resid <= 1e-12
+
+
+# ---------------------------------------------------------------- PM pieces
+
+def test_deposit_bruteforce_and_uniform_lattice():
+    n, box = 8, 16.0
+    rng = np.random.default_rng(3)
+    pos = rng.uniform(0, box, size=(3, 50))
+    grid = pm.cic_deposit_fixed(pos, n, box)
+    ref = np.zeros((n, n, n), dtype=np.int64)
+    for p in range(pos.shape[1]):
+        s = [float(pos[d, p]) * (n / box) for d in range(3)]
+        cell = [math.floor(v) for v in s]
+        f = [s[d] - cell[d] for d in range(3)]
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    wx = (1 - f[0]) if a == 0 else f[0]
+                    wy = (1 - f[1]) if b == 0 else f[1]
+                    wz = (1 - f[2]) if c == 0 else f[2]
+                    q = int(np.rint((wx * wy) * wz * 2.0 ** 40))
+                    ref[(cell[0] + a) % n, (cell[1] + b) % n, (cell[2] + c) % n] += q
+    assert np.array_equal(grid, ref)
+    assert abs(int(grid.sum()) - 50 * 2 ** 40) <= 4 * 50
+    # particles at cell centres of a lattice: every node gets 8 x 1/8 -> delta == 0
+    q1 = (np.arange(n) + 0.5) * box / n
+    qx, qy, qz = np.meshgrid(q1, q1, q1, indexing='ij')
+    lat = np.stack([qx.ravel(), qy.ravel(), qz.ravel()])
+    g2, d2 = pm.deposit(lat, n, box)
+    assert np.all(g2 == 2 ** 40) and np.all(d2 == 0.0)
+    # order independence
+    perm = rng.permutation(pos.shape[1])
+    assert np.array_equal(pm.cic_deposit_fixed(pos[:, perm], n, box), grid)
+
+
+def test_interpolation_reproduces_linear_field():
+    n, box = 16, 32.0
+    x = np.arange(n) * box / n
+    f = 0.3 * x[:, None, None] - 0.7 * x[None, :, None] + 1.1 * x[None, None, :] + 2.0
+    rng = np.random.default_rng(4)
+    pos = rng.uniform(2.0, box - 2.0 - box / n, size=(3, 200))
+    got = pm.cic_interpolate(f[None], pos, box)[0]
+    want = 0.3 * pos[0] - 0.7 * pos[1] + 1.1 * pos[2] + 2.0
+    assert np.max(np.abs(got - want)) < 1e-12
+
+
+def test_grh_force_conserves_momentum():
+    n, box = 16, 64.0
+    pos, _ = inputs.zeldovich_load(n, box, 5, rms_disp=3.0)
+    _, delta = pm.deposit(pos, n, box)
+    prm = params()
+    f, _ = pm.pm_forces(delta, None, pos, box, prm, OM0, 0.5, pm.FORCE_GRH)
+    assert np.max(np.abs(f.sum(axis=1))) < 1e-9 * np.max(np.abs(f)) * pos.shape[1]
+
+
+def test_plane_wave_potentials_closed_form():
+    """Plane wave delta = eps cos(k0 x).  GRH (Eq. GRPoisson): phi = -(3/2) Om(a) delta / kbar0^2.
+    nlDGP (Eq. FullDGP1 with the planar solution u = A (1 - beta/kb) delta / (alpha - gamma/kb)):
+    -(kb^2 + kb/eta) phi = (3/2) Om delta - u/(2 eta) + c2 u / kb.  Force g = -(c/H0)^2 dphi/dx."""
+    n, box, a = 16, 256.0, 0.5
+    c = cos.coefficients(OM0, a)
+    prm = params(a=a)
+    x = np.arange(n) * box / n
+    m0, amp = 2, 0.05
+    k0 = 2 * np.pi * m0 / box
+    delta = amp * np.cos(k0 * x)[:, None, None] * np.ones((n, n, n))
+    kb = (2997.92458 / (a * c.E)) * k0
+    om = 1.5 * (c.eta - 1) / c.eta
+    phi_grh = -om * amp / kb ** 2
+    u_amp = c.A * (1 - c.beta / kb) / (c.alpha - c.gamma / kb) * amp
+    phi_dgp = -(om * amp - u_amp / (2 * c.eta) + c.c2 * u_amp / kb) / (kb ** 2 + kb / c.eta)
+    for mode, ph, u in ((pm.FORCE_GRH, phi_grh, None), (pm.FORCE_NLDGP, phi_dgp, delta / amp * u_amp)):
+        phik = pm.phi_spectrum(delta, u, box, prm, OM0, a, mode)
+        phi = sp.ifft3(phik, n)
+        assert np.max(np.abs(phi - ph * np.cos(k0 * x)[:, None, None])) < 1e-12 * abs(ph)
+        g = pm.force_mesh(phik, box)
+        want = -(2997.92458 ** 2) * (-ph * k0) * np.sin(k0 * x)[:, None, None]
+        assert np.max(np.abs(g[0] - want)) < 1e-10 * np.max(np.abs(want))
+        assert np.max(np.abs(g[1:])) < 1e-12 * np.max(np.abs(want))
+
+
+def test_kick_drift_closed_form():
+    box, a, dlna = 100.0, 0.5, 0.005
+    pos = np.array([[99.99], [10.0], [0.001]])
+    vel = np.array([[3.0], [-2.0], [-5.0]])
+    force = np.array([[100.0], [0.0], [-40.0]])
+    x, v = pm.kick_drift(pos, vel, force, a, dlna, OM0, box)
+    e_n = cos.hubble_E(OM0, a)
+    ah = a * math.exp(dlna / 2)
+    eh = cos.hubble_E(OM0, ah)
+    vv = vel + dlna * force / e_n
+    xx = (pos + dlna * vv / (ah * ah * eh)) % box
+    assert np.allclose(v, vv, rtol=0, atol=1e-14) and np.allclose(x, xx, rtol=0, atol=1e-12)
+
+
+def test_power_spectrum_plane_wave_and_counts():
+    n, box = 16, 100.0
+    x = np.arange(n) * box / n
+    m = (2, 1, 0)
+    eps_amp = 0.3
+    delta = eps_amp * np.cos(2 * np.pi * (m[0] * x[:, None, None] + m[1] * x[None, :, None]) / box) * np.ones((n, n, n))
+    pk, cnt, _ = power.power_spectrum(delta, box)
+    # brute-force mode counting over the full FFT grid
+    f = np.fft.fftfreq(n, 1.0 / n)
+    msq = (f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2).ravel()
+    t = power.bin_thresholds(n)
+    cnt_bf = np.array([np.sum((msq >= t[b]) & (msq < t[b + 1])) for b in range(64)])
+    assert np.array_equal(cnt, cnt_bf)
+    b = int(np.searchsorted(t, 5, side='right') - 1)
+    assert abs(pk[b] - box ** 3 * eps_amp ** 2 / (2 * cnt[b])) < 1e-12 * pk[b]
+    others = np.delete(pk, b)
+    assert np.max(np.abs(others)) < 1e-20
+
+
+# ---------------------------------------------------------------- adjoints
+
+def test_adjoint_dot_product_and_picard_8():
+    n, box = 8, 16.0
+    delta, prm, _ = _c1_like(n, box, 1.0, 31, 3.0, tol=1e-14, max_iter=200)
+    u, _ = fld.solve(delta, box, prm)
+    rng = np.random.default_rng(32)
+    v = rng.standard_normal((n, n, n))
+    g = rng.standard_normal((n, n, n))
+    jv = adjoint.jvp_solution(u, v, box, prm)
+    mu, gd = adjoint.adjoint_dense(u, g, box, prm)
+    assert abs(np.sum(jv * g) - np.sum(v * gd)) < 1e-11 * abs(np.sum(jv * g))
+    mu2, gd2, hist = adjoint.adjoint_picard(u, g, box, prm, tol=1e-13)
+    assert hist[-1] < 1e-13
+    assert np.max(np.abs(gd2 - gd)) < 1e-10 * np.max(np.abs(gd))
+
+
+def test_adjoint_against_central_fd_16():
+    n, box = 16, 32.0
+    delta, prm, _ = _c1_like(n, box, 1.0, 33, 3.0, tol=1e-14, max_iter=300)
+    rng = np.random.default_rng(34)
+    target = np.abs(rng.standard_normal(64)) * 1e-12
+    u, _ = fld.solve(delta, box, prm)
+    pk, _, _ = power.power_spectrum(fld.c_from_u(u, box, prm), box)
+    wts = np.where(pk > 0, 1.0 / np.where(pk > 0, pk, 1.0) ** 2, 0.0)
+    loss, gu = adjoint.c_power_loss(u, box, prm, target, wts)
+    _, gd, _ = adjoint.adjoint_picard(u, gu, box, prm, tol=1e-13)
+    cells = inputs.random_cells(n, 6, 35)
+    h = 1e-4
+    for c in cells:
+        dp = delta.copy().ravel(); dp[c] += h
+        dm = delta.copy().ravel(); dm[c] -= h
+        lp = adjoint.c_power_loss(fld.solve(dp.reshape(delta.shape), box, prm)[0], box, prm, target, wts)[0]
+        lm = adjoint.c_power_loss(fld.solve(dm.reshape(delta.shape), box, prm)[0], box, prm, target, wts)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - gd.ravel()[c]) < 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(gd)))
+
+
+def test_cic_adjoints_against_fd():
+    n, box = 8, 16.0
+    rng = np.random.default_rng(36)
+    pos = rng.uniform(0, box, size=(3, 20))
+    gmesh = rng.standard_normal((n, n, n))
+    mesh = rng.standard_normal((3, n, n, n))
+    gout = rng.standard_normal((3, 20))
+    gp = adjoint.deposit_backward(pos, gmesh, box)
+    gpi, gm = adjoint.interp_backward(mesh, pos, gout, box)
+    h = 1e-6
+
+    def dep_loss(p):
+        (i0, i1), (w0, w1) = pm._cell_and_weights(p, n, box)
+        tot = 0.0
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    wgt = (w0, w1)[a][0] * (w0, w1)[b][1] * (w0, w1)[c][2]
+                    tot += np.sum(wgt * gmesh[(i0, i1)[a][0], (i0, i1)[b][1], (i0, i1)[c][2]])
+        return tot * n ** 3 / p.shape[1]
+
+    for d in range(3):
+        for pidx in range(5):
+            pp = pos.copy(); pp[d, pidx] += h
+            pm_ = pos.copy(); pm_[d, pidx] -= h
+            fd = (dep_loss(pp) - dep_loss(pm_)) / (2 * h)
+            assert abs(fd - gp[d, pidx]) < 1e-6 * max(1.0, abs(fd))
+            fi = (np.sum(pm.cic_interpolate(mesh, pp, box) * gout) - np.sum(pm.cic_interpolate(mesh, pm_, box) * gout)) / (2 * h)
+            assert abs(fi - gpi[d, pidx]) < 1e-6 * max(1.0, abs(fi))
+    # mesh adjoint: <interp(mesh), gout> = <mesh, gm>
+    assert abs(np.sum(pm.cic_interpolate(mesh, pos, box) * gout) - np.sum(mesh * gm)) < 1e-10
