@@ -1,0 +1,200 @@
+"""Benchmark: DGP field solve inside a PM step on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): a 256^3 periodic
+mesh, box 512 Mpc/h, with a 256^3-particle Zel'dovich load (seeded Gaussian
+field, P(k) ~ k^-1.5 exp(-k^2/k_c^2), k_c = 1 h/Mpc, rms displacement 2 Mpc/h),
+z = 1 (a = 0.5), Omega_m0 = 0.27, w = 1/3.  One step = CIC deposit -> field solve
+from the linear guess to normalised residual 1e-8 -> modified-Poisson forces ->
+CIC interpolation + leapfrog kick-drift.  Inputs are resident on the GPU before
+the timed region; particles advance from step to step.
+
+The solve runs in the precision form (float32 FFTs and pointwise storage,
+float64 residual / discriminant / root / reductions, float64 polish); the plain
+float64 form is timed on the same load for the FP32-vs-FP64 comparison.
+
+value = field-solve cells*iterations per second over whole PM steps:
+N^3 x (relaxation passes executed) / (step wall time).  One JSON line on stdout.
+"""
+import argparse
+import json
+import math
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+N, BOX, SEED, A, OM0 = 256, 512.0, 3, 0.5, 0.27
+TOL = 1e-8
+RNL = 1.78          # nonlinear ratio lambda max|u_lin| / alpha (screened; see the design doc for the choice)
+DLNA = 0.005
+PEAK_HBM = 8.0e12   # bytes/s, MI355X
+
+
+def algorithmic_bytes(cls, n, elem):
+    """Bytes one launch of a relaxation-pass kernel must move (one batch element)."""
+    hs = (n // 2 + 1) * n * n
+    n3 = n ** 3
+    c = 2 * elem
+    return {
+        "axis1_fwd": 2 * hs * c,                 # read + write one half spectrum
+        "fanout": 7 * hs * c,                    # read 1, write 6 spectra
+        "axis1_inv": 12 * hs * c,                # 6 spectra read + write
+        "relax": 7 * hs * c + 3 * n3 * elem,     # read 6 spectra, u, S; write u, 1 spectrum
+    }.get(cls)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain float64 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the field solve is built for a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0906_4548_amd import dgp, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED)
+    npart = pos_h.shape[1]
+    pos0 = torch.from_numpy(pos_h).to(dev)
+    prm0 = dgp.params(OM0, A)
+    growth = A * A * prm0.E * ((prm0.eta - 1.0) / prm0.eta) ** 0.55
+    vel0 = torch.from_numpy(growth * psi_h).to(dev)
+
+    # nonlinear coefficient: lambda = RNL alpha / max|u_lin|, u_lin from the library (zero updates)
+    with dgp.Plan(N, BOX) as p64:
+        delta = torch.zeros(N ** 3, dtype=torch.float64, device=dev)
+        p64.deposit(pos0, None, delta)
+        ulin = torch.zeros_like(delta)
+        p64.solve_field(dgp.params(OM0, A, tol=0.0, max_iter=0), delta, ulin)
+        lam = RNL * prm0.alpha / float(ulin.abs().max())
+    del delta, ulin
+
+    def run_form(precision, steps, warmup):
+        plan = dgp.Plan(N, BOX, precision=precision)
+        prm = dgp.params(OM0, A, lam=lam, tol=TOL, max_iter=200, init=dgp.INIT_LINEAR, check_every=8)
+        pos = pos0.clone()
+        vel = vel0.clone()
+        u = torch.zeros(N ** 3, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            plan.step(prm, pos, vel, u, DLNA)
+        torch.cuda.synchronize()
+        plan.timing(True)
+        infos = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, info = plan.step(prm, pos, vel, u, DLNA)
+            infos.append((st, info))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tim = plan.timing_read()
+        plan.timing(False)
+        plan.close()
+        return dt, infos, tim
+
+    print("bench: timing precision form", file=sys.stderr, flush=True)
+    dt32, infos32, tim32 = run_form(dgp.FP32, args.steps, args.warmup)
+    passes32 = sum(i["passes"] for _, i in infos32)
+    value = N ** 3 * passes32 / dt32
+    res = {
+        "metric": "field-solve cells*iter/s (PM step, 256^3, residual 1e-8, FP32+FP64-polish)",
+        "value": value,
+        "unit": "cells*iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 FFT + f64 pointwise/polish",
+        "data": "synthetic (seeded Zel'dovich load)",
+        "config": {"workload": "Zel'dovich PM step, 256^3 mesh, 256^3 particles, box 512 Mpc/h, z=1, "
+                               "r_nl=%.2f, w=1/3, tol 1e-8 from the linear guess" % RNL,
+                   "mesh": N, "particles": npart, "lambda": lam, "tol": TOL},
+        "solve": {
+            "status": [s for s, _ in infos32],
+            "passes_per_step": passes32 / args.steps,
+            "passes_fp64_per_step": sum(i["passes_fp64"] for _, i in infos32) / args.steps,
+            "resid": [i["resid"] for _, i in infos32],
+            "ms_solve_per_step": sum(i["ms_total"] for _, i in infos32) / args.steps,
+        },
+        "kernels_fp32_form": {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in tim32.items()},
+    }
+    # dominant relaxation kernel of the timed region
+    dom = max((k for k in tim32 if k.rstrip("_fp32") in ("axis1_fwd", "fanout", "axis1_inv", "relax")),
+              key=lambda k: tim32[k][0])
+    base = dom[:-5] if dom.endswith("_fp32") else dom
+    elem = 4 if dom.endswith("_fp32") else 8
+    bpl = algorithmic_bytes(base, N, elem)
+    avg_s = tim32[dom][0] / tim32[dom][1] * 1e-3
+    res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": bpl / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
+                       "unit": "GB/s", "frac": bpl / avg_s / PEAK_HBM, "traffic": None,
+                       "bytes_per_launch": bpl, "avg_us": avg_s * 1e6}
+    gbs = {}
+    for k, (ms, cnt) in tim32.items():
+        b = k[:-5] if k.endswith("_fp32") else k
+        e = 4 if k.endswith("_fp32") else 8
+        bb = algorithmic_bytes(b, N, e)
+        if bb:
+            gbs[k] = bb * cnt / (ms * 1e-3) / 1e9
+    res["kernel_GBps"] = gbs
+
+    if not args.no_fp64:
+        print("bench: timing float64 form", file=sys.stderr, flush=True)
+        dt64, infos64, tim64 = run_form(dgp.FP64, args.steps, args.warmup)
+        passes64 = sum(i["passes"] for _, i in infos64)
+        t32 = sum(i["ms_total"] for _, i in infos32) / args.steps
+        t64 = sum(i["ms_total"] for _, i in infos64) / args.steps
+        res["fp64_form"] = {
+            "value": N ** 3 * passes64 / dt64, "ms_per_step": 1e3 * dt64 / args.steps,
+            "passes_per_step": passes64 / args.steps, "ms_solve_per_step": t64,
+            "status": [s for s, _ in infos64], "resid": [i["resid"] for _, i in infos64],
+            "kernels": {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in tim64.items()},
+        }
+        res["fp32_polish_vs_fp64_solve_speedup"] = t64 / t32 if t32 > 0 else None
+
+    if not args.no_cpu:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(pos_h, lam)
+    print(json.dumps(res))
+
+
+def cpu_baseline(pos_h, lam):
+    """The CPU oracle (NumPy float64, pocketfft, one thread) on a bounded sample:
+    two relaxation passes of the same 256^3 solve, scaled to cells*iter/s."""
+    from oracle import field as fld, pm
+    t0 = time.perf_counter()
+    _, delta = pm.deposit(pos_h, N, BOX)
+    t_dep = time.perf_counter() - t0
+    prm = fld.SolveParams.from_cosmology(OM0, A, lam=lam, tol=TOL)
+    t0 = time.perf_counter()
+    fld.solve(delta, BOX, prm, fixed_iters=0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fld.solve(delta, BOX, prm, fixed_iters=2)
+    t2 = time.perf_counter() - t0
+    per_pass = (t2 - t_setup) / 2.0
+    return {"value": N ** 3 / per_pass, "unit": "cells*iter/s", "cores": 1, "kind": "oracle",
+            "sample": "2 relaxation passes of the 256^3 solve (float64 NumPy, pocketfft, 1 thread; "
+                      "host has %d logical CPUs); deposit %.1f s, setup %.1f s excluded" %
+                      (os.cpu_count() or 0, t_dep, t_setup),
+            "seconds_per_pass": per_pass}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * libdgp -- MI355X (gfx950) field solve of the DGP brane-bending mode inside a
+ * particle-mesh step.  C ABI: plain pointers and sizes only.
+ *
+ * Method: Chan & Scoccimarro, "Large-Scale Structure in Brane-Induced Gravity II.
+ * Numerical Simulations".  The field equations are Eq. FullDGP1 (modified Poisson
+ * equation for the Newtonian potential phi) and Eq. FullDGP2 (fully nonlinear
+ * equation for the brane-bending mode C); the solver is the FFT-relaxation of
+ * Sec. III B with the w-split of Sec. III C; the PM step is Sec. III A.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Device pointers.  Every array argument is a pointer to device memory of
+ *    the current HIP device (the device the plan was created on), except the
+ *    `dgp_params` / `dgp_info` structs, which live in host memory.  All arrays
+ *    belong to the caller; the library never frees them.
+ *  - Layouts.  A mesh field is float64 in C order, [batch][N][N][N], the last
+ *    index fastest; mesh axis d is particle coordinate d.  Particles are SoA,
+ *    [3][np] (x of all particles, then y, then z), float32 or float64 as flagged.
+ *    Mesh node j sits at x = j * L / N; positions lie in [0, L).
+ *  - Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued asynchronously; entry points that iterate (solve, step, backward)
+ *    synchronise the stream to read the convergence scalars and return when their
+ *    outputs are complete.  One plan must not be used by two streams at once.
+ *  - Errors.  Functions return a dgp_status.  Negative values are errors: no
+ *    output is valid and dgp_last_error() (per calling thread) describes it.
+ *    Positive values are warnings: outputs are valid.  Nothing aborts or exits.
+ */
+#ifndef DGP_H
+#define DGP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGP_API_VERSION 1
+
+typedef struct dgp_plan dgp_plan;
+
+typedef enum {
+  DGP_OK = 0,
+  DGP_NOT_CONVERGED = 1,   /* max_iter reached; the minimum-residual iterate is returned */
+  DGP_BAD_POINTS = 2,      /* bad points occurred and the residual stopped decreasing; the
+                              minimum-residual iterate is returned (Sec. III C, Fig. 4 text) */
+  DGP_E_INVALID = -1,      /* bad argument: null pointer, unsupported N, non-finite or out-of-range parameter */
+  DGP_E_NOMEM = -2,        /* device allocation failed */
+  DGP_E_HIP = -3,          /* a HIP runtime call failed */
+  DGP_E_UNSUPPORTED = -4   /* valid request this plan cannot serve (e.g. batch > 1 for a PM step) */
+} dgp_status;
+
+typedef enum { DGP_FP64 = 0, DGP_FP32 = 1 } dgp_precision;
+/* DGP_FP32: FFTs, spectral multipliers and stored fields in float32; residual,
+ * discriminant, root selection, k = 0 / mean handling and reductions in float64;
+ * the solve finishes with float64 passes (polish) so the returned iterate meets
+ * the same float64 normalised-residual tolerance as DGP_FP64. */
+
+typedef enum { DGP_INIT_LINEAR = 0, DGP_INIT_ZERO = 1, DGP_INIT_WARM = 2 } dgp_init;
+typedef enum { DGP_FORCE_NLDGP = 0, DGP_FORCE_LDGP = 1, DGP_FORCE_GRH = 2 } dgp_force_mode;
+
+/* Parameters of one field solve / PM step.  dgp_params_init fills every field
+ * from (Omega_m0, a); callers may then override any of them. */
+typedef struct {
+  double omega_m0;     /* present matter density; the paper uses 0.27 (Sec. III A) */
+  double a;            /* scale factor */
+  /* background and coefficients of Eqs. FullDGP1/FullDGP2 (Sec. II) */
+  double E;            /* H/H0 from Eq. DGPFriedmann with r_c H0 = 1/(1 - Omega_m0) */
+  double eta;          /* r_c H */
+  double alpha;        /* 3 (2 eta^2 - 2 eta + 1) / (eta (2 eta - 1)) */
+  double beta;         /* (2 eta^2 - 2 eta - 1) / (eta (2 eta - 1)) */
+  double A;            /* 3 (eta - 1) / eta, source coefficient of Eq. FullDGP2 */
+  double gamma;        /* 3 beta (eta - 1) / (2 eta - 1), sqrt(-lap) C coefficient of Eq. FullDGP2 */
+  double c2;           /* (3 eta^2 - 5 eta + 1) / (2 eta^2 (2 eta - 1)), sqrt(-lap) C coefficient of Eq. FullDGP1 */
+  double kappa;        /* c / (a H) in Mpc/h: kbar = kappa |k| */
+  /* solver */
+  double lambda;       /* coefficient of the two quadratic terms of Eq. FullDGP2 (1 = paper); > 0 */
+  double w;            /* split of Eq. FullDGP2wpara, in [0, 1); paper: 1/3 */
+  double omega_relax;  /* damping u <- (1-omega) u + omega u_new, in (0, 1]; paper: 1 */
+  double tol;          /* stop when <|R|>/eps <= tol (Eq. normres); paper: 0.01 */
+  int max_iter;        /* maximum number of relaxation updates (>= 0) */
+  int init;            /* dgp_init: starting iterate */
+  int nonlocal;        /* 1 keeps the sqrt(-lap) and lap^{-1/2} terms (paper), 0 drops them */
+  int force_mode;      /* dgp_force_mode used by dgp_pm_forces / dgp_step */
+  int check_every;     /* passes between host reads of the convergence flags (>= 1; default 4) */
+  int reserved;
+} dgp_params;
+
+/* Per-batch-element report of a solve (host memory, one per batch element). */
+typedef struct {
+  int status;          /* dgp_status of this element */
+  int iters;           /* relaxation updates applied to the returned iterate */
+  int passes;          /* residual evaluations executed (float64 + float32) */
+  int passes_fp64;     /* of which in float64 */
+  double resid;        /* <|R|>/eps of the returned iterate (float64 evaluation) */
+  double resid_min;    /* smallest residual seen */
+  double eps;          /* <|S|>, S = A (1 - beta lap^{-1/2}) delta (Eq. normres) */
+  double bad_fraction; /* fraction of bad points in the last update (Sec. III C) */
+  double mean_u;       /* <u> of the returned iterate (diagnostic) */
+  double ms_total;     /* wall time of the call on the stream, ms */
+} dgp_info;
+
+/* Fill *p from (omega_m0, a): background (Eq. DGPFriedmann), coefficients (Sec. II),
+ * lambda = 1, w = 1/3, omega_relax = 1, tol = 0.01, max_iter = 100,
+ * init = DGP_INIT_LINEAR, nonlocal = 1, force_mode = DGP_FORCE_NLDGP, check_every = 4.
+ * Host only.  DGP_E_INVALID if p is NULL, omega_m0 not in (0, 1) or a <= 0. */
+int dgp_params_init(dgp_params* p, double omega_m0, double a);
+
+/* Create a plan for an N^3 periodic mesh of side `box` [Mpc/h], `batch` independent
+ * fields, precision dgp_precision.  N is a power of two in [8, 512].  The plan
+ * allocates its device workspace on the current device (hipMalloc) and frees it
+ * in dgp_plan_destroy.  DGP_E_INVALID on bad sizes, DGP_E_NOMEM on allocation failure. */
+int dgp_plan_create(dgp_plan** plan, int n, int batch, double box, int precision);
+int dgp_plan_destroy(dgp_plan* plan);
+/* Device bytes held by the plan. */
+size_t dgp_plan_device_bytes(const dgp_plan* plan);
+
+/* CIC mass assignment (Sec. III A, Eq. CIC), deterministic.
+ * pos [3][np] (float32 if pos_is_fp32 else float64), np >= 1, batch-1 plans only.
+ * grid_fixed [N^3] int64 (optional, may be NULL): sum over particles of
+ *   rint(W * 2^40) with W = (w_x w_y) w_z, per-axis weights (1 - f, f) in float64;
+ *   identical bits for any particle order.
+ * delta [N^3] float64 (optional): Q 2^-40 N^3/np - 1 with its mean removed. */
+int dgp_deposit(dgp_plan* plan, const void* pos, int pos_is_fp32, long long np, long long* grid_fixed,
+                double* delta, void* stream);
+
+/* Field solve of Eq. FullDGP2 by FFT-relaxation (Sec. III B, Eq. FFTrelax; w-split of
+ * Sec. III C, Eqs. nabla^2Cwpara and Bwpara).
+ * delta   [batch][N^3] float64 density contrast (its mean is ignored: k = 0 multipliers are 0).
+ * u_state [batch][N^3] float64, u = lapbar C.  Read as the starting iterate when
+ *         p->init == DGP_INIT_WARM (warm start from the previous step, Sec. III B);
+ *         always overwritten with the returned iterate.
+ * c_out   [batch][N^3] float64, optional: C = lapbar^{-1} u (C(k) = -u(k)/kbar^2).
+ * info    host array of batch dgp_info, optional.
+ * Returns the worst status over the batch. */
+int dgp_solve_field(dgp_plan* plan, const dgp_params* p, const double* delta, double* u_state, double* c_out,
+                    dgp_info* info, void* stream);
+
+/* Forces on particles from the modified Poisson equation (Eq. FullDGP1; lDGP: its linear
+ * form; GRH: Eq. GRPoisson with the same background) and the spectral gradient i k phi
+ * (Sec. III A), interpolated with the CIC weights.
+ * delta [N^3], u_state [N^3] (the solved u; unused for lDGP/GRH), pos [3][np].
+ * force [3][np] float64 output: g = -(c/H0)^2 grad phi at each particle (H0 = 1, Mpc/h).
+ * phi_n [N^3] float64, optional: phi on the mesh (units of c^2).  Batch-1 plans only. */
+int dgp_pm_forces(dgp_plan* plan, const dgp_params* p, const double* delta, const double* u_state, const void* pos,
+                  int pos_is_fp32, long long np, double* force, double* phi_n, void* stream);
+
+/* One PM step at scale factor p->a: deposit, field solve (u_state in/out, started as
+ * p->init says), forces, CIC interpolation and a leapfrog step in ln a:
+ *   vel += dlna * g / E(a);  pos += dlna * vel / (a_h^2 E(a_h)), a_h = a e^{dlna/2};
+ * positions wrapped into [0, L).  vel holds p = a^2 dx/dt at half steps.
+ * pos, vel [3][np] (float32 if is_fp32), updated in place. */
+int dgp_step(dgp_plan* plan, const dgp_params* p, void* pos, void* vel, int is_fp32, long long np, double dlna,
+             double* u_state, dgp_info* info, void* stream);
+
+/* Implicit adjoint of the converged solve: given g = dL/du at u* (the output of
+ * dgp_solve_field with the same delta and params), solves J^T mu = g by the transposed
+ * relaxation and returns dL/ddelta = S^T mu, S = A (1 - beta/kbar) (k = 0 -> 0).
+ * delta, u_star, grad_u, grad_delta: [batch][N^3] float64.  Uses p->tol as the relative
+ * tolerance on <|J^T mu - g|>/<|g|> and p->max_iter. */
+int dgp_solve_field_backward(dgp_plan* plan, const dgp_params* p, const double* delta, const double* u_star,
+                             const double* grad_u, double* grad_delta, dgp_info* info, void* stream);
+
+/* Adjoint of the CIC deposit with respect to positions (unquantised weights):
+ * grad_pos [3][np] = (N^3/np) sum_c grad_delta[c] dW_c/dx.  Batch-1 plans only. */
+int dgp_deposit_backward(dgp_plan* plan, const void* pos, int pos_is_fp32, long long np, const double* grad_delta,
+                         double* grad_pos, void* stream);
+
+/* Binned power spectrum of a mesh field ([batch][N^3]), or, with of_c = 1, of
+ * C = lapbar^{-1} u for a field u.  nbins logarithmic bins between 2 pi/L and the
+ * Nyquist pi N/L (mode m in bin b when T_b <= |m|^2 < T_{b+1}, T_b = ceil((N/2)^(2b/nbins))),
+ * P_b = (L^3/N^6) <|F(k)|^2>.  pk [batch][nbins] and counts [nbins] (optional, mode
+ * multiplicities) are HOST arrays; the call synchronises the stream.  nbins in [1, 128]. */
+int dgp_power_spectrum(dgp_plan* plan, const dgp_params* p, const double* field, int of_c, int nbins, double* pk,
+                       double* counts, void* stream);
+
+/* Gradient of sum_b grad_pk[b] P_b with respect to the field.  grad_pk: HOST array
+ * [batch][nbins]; field, grad_field: device [batch][N^3]. */
+int dgp_power_spectrum_backward(dgp_plan* plan, const dgp_params* p, const double* field, int of_c, int nbins,
+                                const double* grad_pk, double* grad_field, void* stream);
+
+/* 3D real FFT of [batch][N^3] float64 (forward, unnormalised) into the plan's half
+ * spectrum layout [batch][N/2+1][N][N] complex (interleaved re, im; half axis = axis 0),
+ * and its inverse (carries 1/N^3).  For tests of the transform itself. */
+int dgp_fft_forward(dgp_plan* plan, const double* field, double* spectrum, void* stream);
+int dgp_fft_inverse(dgp_plan* plan, const double* spectrum, double* field, void* stream);
+
+/* Live kernel timing.  When enabled, the plan brackets the launches of each class
+ * below with HIP events on the caller's stream and accumulates their elapsed times
+ * once the stream has been synchronised (every solve / step synchronises before
+ * returning).  Enabling resets the counters.  Classes with the DGP_T_FP32_OFFSET
+ * added are the float32 launches of the precision form. */
+enum {
+  DGP_T_AXIS1_FWD = 0,   /* forward axis-1 pass of the iterate's spectrum, per relaxation pass */
+  DGP_T_FANOUT = 1,      /* axis-2 pass: forward FFT, 6 spectral multipliers, 6 inverse FFTs */
+  DGP_T_AXIS1_INV = 2,   /* inverse axis-1 pass of the 6 spectra */
+  DGP_T_RELAX = 3,       /* fused axis-0 inverse of 6 spectra + pointwise update + axis-0 forward */
+  DGP_T_FINALIZE = 4,    /* residual reduction and stopping rules */
+  DGP_T_SETUP = 5,       /* source S, eps and linear guess from delta */
+  DGP_T_DEPOSIT = 6,     /* CIC deposit and density contrast */
+  DGP_T_FORCES = 7,      /* modified Poisson + gradient: force mesh */
+  DGP_T_INTERP_KICK = 8, /* CIC interpolation fused with the leapfrog update */
+  DGP_T_FP32_OFFSET = 16,
+  DGP_T_NCLASS = 32
+};
+int dgp_timing_enable(dgp_plan* plan, int on);
+/* total_ms / launches (either may be NULL) of one class since the last enable. */
+int dgp_timing_read(dgp_plan* plan, int cls, double* total_ms, long long* launches);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dgp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGP_H */

@@ -1,0 +1,980 @@
+// C-ABI of libdgp: plans, parameters, and the host-side orchestration of the
+// field solve (Sec. III B/C), the PM step (Sec. III A), the adjoints and the
+// binned power spectrum.  Every array step runs in the HIP kernels of
+// passes.hip, relax.hip, adjoint.hip and pm.hip; this file only sequences
+// launches, owns the workspace and reads the few convergence scalars.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dgp.h"
+#include "dgp_internal.h"
+
+using namespace dgp;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(DGP_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+#define LAUNCHCHK()                                                                            \
+  do {                                                                                         \
+    hipError_t e_ = hipGetLastError();                                                         \
+    if (e_ != hipSuccess) return fail(DGP_E_HIP, "kernel launch: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+extern "C" const char* dgp_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ twiddle tables (per device, per N)
+namespace dgp {
+constexpr int kMaxDev = 64;
+constexpr int kLogMin = 3, kLogMax = 9;
+static void* g_tw[kMaxDev][kLogMax + 1][2];   // [dev][log2 n][0 = double, 1 = float]
+static std::mutex g_tw_mu;
+
+static int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+template <typename T>
+const cx<T>* twiddles(int n) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return static_cast<const cx<T>*>(g_tw[dev][ilog2(n)][sizeof(T) == 4 ? 1 : 0]);
+}
+template const cx<double>* twiddles<double>(int);
+template const cx<float>* twiddles<float>(int);
+}  // namespace dgp
+
+// exp(-2 pi i m / n) in double; cos/sin of angles reduced to the first octant by symmetry
+static void twiddle_values(int n, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(n);
+  im.resize(n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int m = 0; m < n; ++m) {
+    const long double ang = two_pi * (long double)m / (long double)n;
+    re[m] = (double)cosl(ang);
+    im[m] = (double)-sinl(ang);
+  }
+  // exact values at the quarter points
+  for (int m = 0; m < n; m += n / 4) {
+    const int qd = m / (n / 4);
+    re[m] = (qd == 0) ? 1.0 : (qd == 2) ? -1.0 : 0.0;
+    im[m] = (qd == 1) ? -1.0 : (qd == 3) ? 1.0 : 0.0;
+  }
+}
+
+static int ensure_twiddles(int n) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev >= kMaxDev) return fail(DGP_E_UNSUPPORTED, "device index %d too large", dev);
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  for (int l = kLogMin; l <= ilog2(n); ++l) {
+    const int nn = 1 << l;
+    if (g_tw[dev][l][0] != nullptr) continue;
+    std::vector<double> re, im;
+    twiddle_values(nn, re, im);
+    std::vector<double> hd(2 * nn);
+    std::vector<float> hf(2 * nn);
+    for (int m = 0; m < nn; ++m) {
+      hd[2 * m] = re[m];
+      hd[2 * m + 1] = im[m];
+      hf[2 * m] = (float)re[m];
+      hf[2 * m + 1] = (float)im[m];
+    }
+    void* dd = nullptr;
+    void* df = nullptr;
+    HIPCHK(hipMalloc(&dd, sizeof(double) * 2 * nn));
+    HIPCHK(hipMalloc(&df, sizeof(float) * 2 * nn));
+    HIPCHK(hipMemcpy(dd, hd.data(), sizeof(double) * 2 * nn, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(df, hf.data(), sizeof(float) * 2 * nn, hipMemcpyHostToDevice));
+    g_tw[dev][l][0] = dd;
+    g_tw[dev][l][1] = df;
+  }
+  return DGP_OK;
+}
+
+// ------------------------------------------------------------------ background (Sec. II)
+static double hubble_E(double om0, double a) {
+  const double b = 1.0 - om0;
+  return 0.5 * (b + std::sqrt(b * b + 4.0 * om0 / (a * a * a)));
+}
+static constexpr double kCOverH0 = 2997.92458;
+
+extern "C" int dgp_params_init(dgp_params* p, double omega_m0, double a) {
+  if (!p) return fail(DGP_E_INVALID, "params is NULL");
+  if (!(omega_m0 > 0.0 && omega_m0 < 1.0) || !(a > 0.0) || !std::isfinite(a))
+    return fail(DGP_E_INVALID, "omega_m0 must be in (0,1) and a > 0");
+  std::memset(p, 0, sizeof *p);
+  p->omega_m0 = omega_m0;
+  p->a = a;
+  const double E = hubble_E(omega_m0, a);
+  const double eta = E / (1.0 - omega_m0);
+  const double den = eta * (2.0 * eta - 1.0);
+  p->E = E;
+  p->eta = eta;
+  p->beta = (2.0 * eta * eta - 2.0 * eta - 1.0) / den;
+  p->alpha = 3.0 * (2.0 * eta * eta - 2.0 * eta + 1.0) / den;
+  p->A = 3.0 * (eta - 1.0) / eta;
+  p->gamma = 3.0 * p->beta * (eta - 1.0) / (2.0 * eta - 1.0);
+  p->c2 = (3.0 * eta * eta - 5.0 * eta + 1.0) / (2.0 * eta * eta * (2.0 * eta - 1.0));
+  p->kappa = kCOverH0 / (a * E);
+  p->lambda = 1.0;
+  p->w = 1.0 / 3.0;
+  p->omega_relax = 1.0;
+  p->tol = 1e-2;
+  p->max_iter = 100;
+  p->init = DGP_INIT_LINEAR;
+  p->nonlocal = 1;
+  p->force_mode = DGP_FORCE_NLDGP;
+  p->check_every = 4;
+  return DGP_OK;
+}
+
+static int check_params(const dgp_params* p) {
+  if (!p) return fail(DGP_E_INVALID, "params is NULL");
+  const double v[] = {p->a, p->E, p->eta, p->alpha, p->beta, p->A, p->gamma, p->c2, p->kappa, p->lambda, p->w,
+                      p->omega_relax, p->tol};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(DGP_E_INVALID, "non-finite parameter");
+  if (!(p->lambda > 0.0)) return fail(DGP_E_INVALID, "lambda must be > 0");
+  if (!(p->w >= 0.0 && p->w < 1.0)) return fail(DGP_E_INVALID, "w must be in [0, 1)");
+  if (!(p->omega_relax > 0.0 && p->omega_relax <= 1.0)) return fail(DGP_E_INVALID, "omega_relax must be in (0, 1]");
+  if (!(p->tol >= 0.0)) return fail(DGP_E_INVALID, "tol must be >= 0");
+  if (p->max_iter < 0 || p->max_iter >= kMaxHist - 1) return fail(DGP_E_INVALID, "max_iter must be in [0, %d)", kMaxHist - 1);
+  if (p->init < 0 || p->init > 2) return fail(DGP_E_INVALID, "bad init");
+  if (p->force_mode < 0 || p->force_mode > 2) return fail(DGP_E_INVALID, "bad force_mode");
+  if (!(p->alpha > 0.0) || !(p->kappa > 0.0) || !(p->eta > 0.0)) return fail(DGP_E_INVALID, "alpha, kappa, eta must be > 0");
+  return DGP_OK;
+}
+
+// ------------------------------------------------------------------ plan
+struct dgp_plan {
+  int n = 0, batch = 0, precision = 0, device = 0;
+  double box = 0.0;
+  size_t n3 = 0, hs = 0;   // real and half-spectrum element counts per field per batch element
+  // float64 solve workspace
+  double* U = nullptr;               // [3][B][n3]
+  double* S = nullptr;               // [B][n3]
+  cx<double>* spec_u = nullptr;      // [B][hs]
+  cx<double>* spec6 = nullptr;       // [6][B][hs]
+  double* partial = nullptr;         // [B][groups][2]
+  int groups64 = 0;
+  // float32 solve workspace (precision form)
+  float* U32 = nullptr;
+  float* S32 = nullptr;
+  cx<float>* spec_u32 = nullptr;
+  cx<float>* spec6_32 = nullptr;
+  double* partial32 = nullptr;
+  int groups32 = 0;
+  // control
+  SolveCtl* ctl = nullptr;           // device [B]
+  SolveCtl* ctl_host = nullptr;      // pinned [B]
+  int* n_active = nullptr;
+  int* n_active_host = nullptr;
+  double* mean_u = nullptr;          // [B]
+  double* vec = nullptr;             // [4][B] scratch scalars (eps, means)
+  double* red = nullptr;             // reduction scratch
+  // PM (batch 1)
+  long long* grid = nullptr;         // [n3]
+  double* delta = nullptr;           // [n3]
+  double* mesh3 = nullptr;           // [3][n3]
+  // power spectrum
+  double* bin_tab = nullptr;         // thresholds + coefficients
+  double* bin_partial = nullptr;
+  double* bin_host = nullptr;        // pinned
+  // adjoint (allocated on first use)
+  double* adj = nullptr;             // [13][B][n3]
+  std::vector<void*> dev_allocs;
+  std::vector<void*> host_allocs;
+  size_t bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // live per-kernel timing (HIP events around launches on the caller's stream)
+  bool timing = false;
+  struct Pend { hipEvent_t a, b; int cls; };
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pend> pend;
+  double t_ms[DGP_T_NCLASS] = {};
+  long long t_cnt[DGP_T_NCLASS] = {};
+};
+
+static hipEvent_t ev_get(dgp_plan* pl) {
+  if (!pl->ev_pool.empty()) {
+    hipEvent_t e = pl->ev_pool.back();
+    pl->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Scope that brackets the launches it encloses with two events when timing is on.
+struct Timed {
+  dgp_plan* pl;
+  hipStream_t s;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(dgp_plan* p, hipStream_t st, int c) : pl(p), s(st), cls(c) {
+    if (pl->timing && (a = ev_get(pl)) != nullptr) (void)hipEventRecord(a, s);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = ev_get(pl);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    pl->pend.push_back({a, b, cls});
+  }
+};
+
+// accumulate completed event pairs (call after the stream has been synchronised)
+static void timing_flush(dgp_plan* pl) {
+  for (auto& q : pl->pend) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+      pl->t_ms[q.cls] += ms;
+      pl->t_cnt[q.cls] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    pl->ev_pool.push_back(q.a);
+    pl->ev_pool.push_back(q.b);
+  }
+  pl->pend.clear();
+}
+
+template <typename T>
+static constexpr int tcls(int base) { return base + (sizeof(T) == 4 ? DGP_T_FP32_OFFSET : 0); }
+
+template <typename T>
+static int dalloc(dgp_plan* pl, T** ptr, size_t count) {
+  void* p = nullptr;
+  const size_t bytes = sizeof(T) * (count ? count : 1);
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGP_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+  }
+  pl->dev_allocs.push_back(p);
+  pl->bytes += bytes;
+  *ptr = static_cast<T*>(p);
+  return DGP_OK;
+}
+
+template <typename T>
+static int halloc(dgp_plan* pl, T** ptr, size_t count) {
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sizeof(T) * (count ? count : 1), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DGP_E_NOMEM, "hipHostMalloc failed");
+  }
+  pl->host_allocs.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return DGP_OK;
+}
+
+static void plan_free(dgp_plan* pl) {
+  for (auto& q : pl->pend) {
+    (void)hipEventDestroy(q.a);
+    (void)hipEventDestroy(q.b);
+  }
+  for (hipEvent_t e : pl->ev_pool) (void)hipEventDestroy(e);
+  for (void* p : pl->dev_allocs) (void)hipFree(p);
+  for (void* p : pl->host_allocs) (void)hipHostFree(p);
+  if (pl->ev0) (void)hipEventDestroy(pl->ev0);
+  if (pl->ev1) (void)hipEventDestroy(pl->ev1);
+  delete pl;
+}
+
+#define TRY(expr)               \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ < 0) return r_;      \
+  } while (0)
+
+static int plan_alloc(dgp_plan* pl) {
+  const size_t B = pl->batch, n3 = pl->n3, hs = pl->hs;
+  TRY(dalloc(pl, &pl->U, 3 * B * n3));
+  TRY(dalloc(pl, &pl->S, B * n3));
+  TRY(dalloc(pl, &pl->spec_u, B * hs));
+  TRY(dalloc(pl, &pl->spec6, 6 * B * hs));
+  pl->groups64 = relax_groups(pl->n, 8);
+  TRY(dalloc(pl, &pl->partial, B * pl->groups64 * 2));
+  if (pl->precision == DGP_FP32) {
+    TRY(dalloc(pl, &pl->U32, 3 * B * n3));
+    TRY(dalloc(pl, &pl->S32, B * n3));
+    TRY(dalloc(pl, &pl->spec_u32, B * hs));
+    TRY(dalloc(pl, &pl->spec6_32, 6 * B * hs));
+    pl->groups32 = relax_groups(pl->n, 4);
+    TRY(dalloc(pl, &pl->partial32, B * pl->groups32 * 2));
+  }
+  TRY(dalloc(pl, &pl->ctl, B));
+  TRY(halloc(pl, &pl->ctl_host, B));
+  TRY(dalloc(pl, &pl->n_active, 1));
+  TRY(halloc(pl, &pl->n_active_host, 1));
+  TRY(dalloc(pl, &pl->mean_u, B));
+  TRY(dalloc(pl, &pl->vec, 4 * B));
+  TRY(dalloc(pl, &pl->red, absmean_scratch_doubles(n3, (int)B) + 16));
+  if (B == 1) {
+    TRY(dalloc(pl, &pl->grid, n3));
+    TRY(dalloc(pl, &pl->delta, n3));
+    TRY(dalloc(pl, &pl->mesh3, 3 * n3));
+  }
+  TRY(dalloc(pl, &pl->bin_tab, 129 + 128 * B));
+  TRY(dalloc(pl, &pl->bin_partial, (size_t)p3_row_groups(pl->n) * B * 2 * 128));
+  TRY(halloc(pl, &pl->bin_host, (size_t)p3_row_groups(pl->n) * B * 2 * 128));
+  return DGP_OK;
+}
+
+extern "C" int dgp_plan_create(dgp_plan** out, int n, int batch, double box, int precision) {
+  if (!out) return fail(DGP_E_INVALID, "plan pointer is NULL");
+  *out = nullptr;
+  if (n < 8 || n > 512 || (n & (n - 1)) != 0) return fail(DGP_E_INVALID, "N must be a power of two in [8, 512], got %d", n);
+  if (batch < 1 || batch > 4096) return fail(DGP_E_INVALID, "batch must be in [1, 4096]");
+  if (!(box > 0.0) || !std::isfinite(box)) return fail(DGP_E_INVALID, "box must be > 0");
+  if (precision != DGP_FP64 && precision != DGP_FP32) return fail(DGP_E_INVALID, "bad precision");
+  dgp_plan* pl = new dgp_plan;
+  pl->n = n;
+  pl->batch = batch;
+  pl->box = box;
+  pl->precision = precision;
+  pl->n3 = (size_t)n * n * n;
+  pl->hs = (size_t)(n / 2 + 1) * n * n;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    delete pl;
+    return fail(DGP_E_HIP, "hipGetDevice failed");
+  }
+  int r = ensure_twiddles(n);
+  if (r == DGP_OK) r = plan_alloc(pl);
+  if (r == DGP_OK && (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess))
+    r = fail(DGP_E_HIP, "hipEventCreate failed");
+  if (r != DGP_OK) {
+    plan_free(pl);
+    return r;
+  }
+  *out = pl;
+  return DGP_OK;
+}
+
+extern "C" int dgp_plan_destroy(dgp_plan* pl) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  plan_free(pl);
+  return DGP_OK;
+}
+
+extern "C" size_t dgp_plan_device_bytes(const dgp_plan* pl) { return pl ? pl->bytes : 0; }
+
+// ------------------------------------------------------------------ helpers
+static SpecCoef spec_coef(const dgp_plan* pl, const dgp_params* p) {
+  SpecCoef c{};
+  const bool nl = p->nonlocal != 0;
+  c.kf = 2.0 * M_PI / pl->box;
+  c.kappa = p->kappa;
+  c.A = p->A;
+  c.beta = nl ? p->beta : 0.0;
+  c.alpha = p->alpha;
+  c.gamma = nl ? p->gamma : 0.0;
+  c.om15 = 1.5 * (p->eta - 1.0) / p->eta;
+  c.inv2eta = 1.0 / (2.0 * p->eta);
+  c.c2 = nl ? p->c2 : 0.0;
+  c.inv_eta_nl = nl ? 1.0 / p->eta : 0.0;
+  c.force_scale = kCOverH0 * kCOverH0;
+  c.inv_n3 = 1.0 / double(pl->n3);
+  c.lam2 = 2.0 * p->lambda;
+  c.force_mode = p->force_mode;
+  c.with_phi = 0;
+  c.power_c = 0;
+  c.nbins = 64;
+  return c;
+}
+
+static SolveCfg solve_cfg(const dgp_plan* pl, const dgp_params* p, double tol, int max_iter) {
+  SolveCfg c{};
+  c.lam = p->lambda;
+  c.w = p->w;
+  c.alpha = p->alpha;
+  c.gamma = p->nonlocal ? p->gamma : 0.0;
+  c.omega = p->omega_relax;
+  c.tol = tol;
+  c.max_iter = max_iter;
+  c.n = pl->n;
+  c.batch = pl->batch;
+  return c;
+}
+
+// 3D forward transform of real fields [nb][n3] -> half spectrum [nb][hs] (axis 0 last index order kept)
+template <typename T>
+static int fwd3(dgp_plan* pl, const T* in, cx<T>* spec, int nb, const SolveCtl* ctl, hipStream_t s) {
+  launch_p1_fwd<T>(pl->n, in, spec, nb, ctl, s);
+  launch_p2<T>(pl->n, spec, 1, nb, -1, ctl, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+// ------------------------------------------------------------------ the relaxation (one precision)
+template <typename T>
+struct Ws {
+  T* U;
+  T* S;
+  cx<T>* spec_u;
+  cx<T>* spec6;
+  double* partial;
+  int groups;
+};
+
+static Ws<double> ws64(dgp_plan* pl) { return {pl->U, pl->S, pl->spec_u, pl->spec6, pl->partial, pl->groups64}; }
+static Ws<float> ws32(dgp_plan* pl) { return {pl->U32, pl->S32, pl->spec_u32, pl->spec6_32, pl->partial32, pl->groups32}; }
+
+// S and the linear guess from delta (float64 source spectrum, written in precision T).
+template <typename T>
+static int setup_source(dgp_plan* pl, const dgp_params* p, const T* delta_t, Ws<T>& w, bool want_linear,
+                        hipStream_t s) {
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  const SpecCoef cf = spec_coef(pl, p);
+  Timed tm(pl, s, tcls<T>(DGP_T_SETUP));
+  TRY(fwd3<T>(pl, delta_t, w.spec_u, B, nullptr, s));
+  launch_p3<T>(n, SPEC_SOURCE, w.spec_u, fs, 1, w.spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
+  launch_p2<T>(n, w.spec6, 2, B, +1, nullptr, s);
+  launch_p1_inv<T>(n, w.spec6, w.S, B, nullptr, s);
+  if (want_linear) launch_p1_inv<T>(n, w.spec6 + fs, w.U, B, nullptr, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+// enqueue one relaxation pass on the iterate whose axis-0..1 spectrum is in spec_u
+template <typename T>
+static int enqueue_pass(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg& cfg, hipStream_t s) {
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  const SpecCoef cf = spec_coef(pl, p);
+  {
+    Timed t(pl, s, tcls<T>(DGP_T_AXIS1_FWD));
+    launch_p2<T>(n, w.spec_u, 1, B, -1, pl->ctl, s);
+  }
+  {
+    Timed t(pl, s, tcls<T>(DGP_T_FANOUT));
+    launch_p3<T>(n, SPEC_FANOUT6, w.spec_u, fs, 1, w.spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, pl->ctl, s);
+  }
+  {
+    Timed t(pl, s, tcls<T>(DGP_T_AXIS1_INV));
+    launch_p2<T>(n, w.spec6, 6, B, +1, pl->ctl, s);
+  }
+  {
+    Timed t(pl, s, tcls<T>(DGP_T_RELAX));
+    launch_relax<T>(n, w.spec6, w.U, w.S, w.spec_u, w.partial, pl->mean_u, B, cfg, pl->ctl, s);
+  }
+  {
+    Timed t(pl, s, tcls<T>(DGP_T_FINALIZE));
+    launch_finalize(w.partial, w.groups, pl->ctl, cfg, pl->n_active, s);
+  }
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+// Run passes until every batch element is done.  The host reads the control
+// blocks between chunks and sizes the next chunk from the observed linear
+// convergence rate, so few passes are launched after the last element has
+// stopped (such launches exit at once but still cost a launch).
+template <typename T>
+static int run_loop(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg& cfg, hipStream_t s, int* passes) {
+  const int B = pl->batch;
+  const int cap = p->check_every > 0 ? p->check_every : 4;
+  int k = 0;
+  int chunk = std::min(2, cfg.max_iter + 1);
+  for (;;) {
+    for (int i = 0; i < chunk && k <= cfg.max_iter; ++i, ++k) TRY(enqueue_pass<T>(pl, p, w, cfg, s));
+    HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    timing_flush(pl);
+    int active = 0, next = cap;
+    for (int b = 0; b < B; ++b) {
+      const SolveCtl& C = pl->ctl_host[b];
+      if (C.done) continue;
+      ++active;
+      int m = 1;
+      const int n = C.iters;   // the next pass evaluates iterate n; hist[n-1], hist[n-2] are known
+      if (n >= 2 && n - 1 < kMaxHist) {
+        const double r1 = C.hist[n - 1], r0 = C.hist[n - 2];
+        if (r1 > 0.0 && r0 > r1 && cfg.tol > 0.0) {
+          const double need = std::log(cfg.tol / r1) / std::log(r1 / r0);
+          m = need <= 1.0 ? 1 : int(std::ceil(need));
+        }
+      }
+      next = std::min(next, std::max(1, m));
+    }
+    if (active == 0 || k > cfg.max_iter) break;
+    chunk = next;
+  }
+  *passes = k;
+  return DGP_OK;
+}
+
+static int status_rank(int st) { return st == DGP_OK ? 0 : (st == DGP_NOT_CONVERGED ? 2 : 1); }
+
+// Copy the decided iterates into u_state and fill info; returns the worst status.
+template <typename T>
+static int collect(dgp_plan* pl, Ws<T>& w, double* u_state, dgp_info* info, int passes_fp64, hipStream_t s) {
+  const int B = pl->batch;
+  HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int worst = DGP_OK;
+  for (int b = 0; b < B; ++b) {
+    const SolveCtl& C = pl->ctl_host[b];
+    const T* src = w.U + ((size_t)C.result * B + b) * pl->n3;
+    if constexpr (sizeof(T) == 8) {
+      HIPCHK(hipMemcpyAsync(u_state + (size_t)b * pl->n3, src, sizeof(double) * pl->n3, hipMemcpyDeviceToDevice, s));
+    } else {
+      launch_convert<double>(pl->n3, src, 1, u_state + (size_t)b * pl->n3, s);
+    }
+    const int st = C.status;
+    if (status_rank(st) > status_rank(worst)) worst = st;
+  }
+  LAUNCHCHK();
+  if (info) {
+    launch_absmean<double>(pl->n3, u_state, B, pl->red, pl->vec, pl->vec + B, s);
+    std::vector<double> means(B);
+    HIPCHK(hipMemcpyAsync(means.data(), pl->vec + B, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b) {
+      const SolveCtl& C = pl->ctl_host[b];
+      info[b].status = C.status;
+      info[b].iters = C.iters;
+      info[b].passes = C.passes;
+      info[b].passes_fp64 = passes_fp64 >= 0 ? passes_fp64 : C.passes;
+      info[b].resid = C.resid;
+      info[b].resid_min = C.resid_min;
+      info[b].eps = C.eps;
+      info[b].bad_fraction = C.bad_frac;
+      info[b].mean_u = means[b];
+    }
+  }
+  return worst;
+}
+
+// C = lapbar^{-1} u for [B] fields
+static int c_field(dgp_plan* pl, const dgp_params* p, const double* u, double* c_out, hipStream_t s) {
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  const SpecCoef cf = spec_coef(pl, p);
+  TRY(fwd3<double>(pl, u, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_CFIELD, pl->spec_u, fs, 1, pl->spec6, fs, 1, B, cf, nullptr, nullptr, nullptr, nullptr, s);
+  launch_p2<double>(n, pl->spec6, 1, B, +1, nullptr, s);
+  launch_p1_inv<double>(n, pl->spec6, c_out, B, nullptr, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+// plain float64 solve from the chosen initial iterate
+static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
+                   hipStream_t s) {
+  Ws<double> w = ws64(pl);
+  const int B = pl->batch;
+  TRY(setup_source<double>(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
+  if (p->init == DGP_INIT_WARM) {
+    HIPCHK(hipMemcpyAsync(w.U, u_state, sizeof(double) * B * pl->n3, hipMemcpyDeviceToDevice, s));
+  } else if (p->init == DGP_INIT_ZERO) {
+    HIPCHK(hipMemsetAsync(w.U, 0, sizeof(double) * B * pl->n3, s));
+  }
+  launch_absmean<double>(pl->n3, w.S, B, pl->red, pl->vec, nullptr, s);
+  launch_ctl_init(pl->ctl, pl->vec, B, s);
+  // a pass starts from the axis-0 spectrum of its iterate (what the fused pass writes)
+  launch_p1_fwd<double>(pl->n, w.U, w.spec_u, B, nullptr, s);
+  const SolveCfg cfg = solve_cfg(pl, p, p->tol, p->max_iter);
+  int passes = 0;
+  TRY(run_loop<double>(pl, p, w, cfg, s, &passes));
+  return collect<double>(pl, w, u_state, info, -1, s);
+}
+
+int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
+                   hipStream_t s);
+
+extern "C" int dgp_solve_field(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, double* c_out,
+                               dgp_info* info, void* stream) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  TRY(check_params(p));
+  if (!delta || !u_state) return fail(DGP_E_INVALID, "delta and u_state are required");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipEventRecord(pl->ev0, s));
+  int st;
+  if (pl->precision == DGP_FP32)
+    st = solve32_polish(pl, p, delta, u_state, info, s);
+  else
+    st = solve64(pl, p, delta, u_state, info, s);
+  if (st < 0) return st;
+  if (c_out) TRY(c_field(pl, p, u_state, c_out, s));
+  HIPCHK(hipEventRecord(pl->ev1, s));
+  HIPCHK(hipEventSynchronize(pl->ev1));
+  timing_flush(pl);
+  if (info) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+    for (int b = 0; b < pl->batch; ++b) info[b].ms_total = ms;
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------ precision form: float32 passes + float64 polish
+// Phase 1 runs float32 relaxation passes (float64 pointwise arithmetic and
+// reductions) from the linear guess until the float32 residual reaches
+// max(tol, switch_tol) or stalls; phase 2 continues with float64 passes from that
+// iterate until the float64 residual meets tol.  The returned residual is
+// always a float64 evaluation.
+int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
+                   hipStream_t s) {
+  const int B = pl->batch;
+  const size_t n3 = pl->n3;
+  Ws<float> w32 = ws32(pl);
+  // float32 copies of delta
+  launch_convert<float>(B * n3, delta, 0, w32.U + 2 * B * n3, s);   // use the third buffer as scratch
+  TRY(setup_source<float>(pl, p, w32.U + 2 * B * n3, w32, p->init == DGP_INIT_LINEAR, s));
+  if (p->init == DGP_INIT_WARM) {
+    launch_convert<float>(B * n3, u_state, 0, w32.U, s);
+  } else if (p->init == DGP_INIT_ZERO) {
+    HIPCHK(hipMemsetAsync(w32.U, 0, sizeof(float) * B * n3, s));
+  }
+  launch_absmean<float>(n3, w32.S, B, pl->red, pl->vec, nullptr, s);
+  launch_ctl_init(pl->ctl, pl->vec, B, s);
+  launch_p1_fwd<float>(pl->n, w32.U, w32.spec_u, B, nullptr, s);
+  const double switch_tol = std::max(p->tol, 1e-6);
+  SolveCfg cfg32 = solve_cfg(pl, p, switch_tol, p->max_iter);
+  int passes32 = 0;
+  TRY(run_loop<float>(pl, p, w32, cfg32, s, &passes32));
+  // float32 result -> float64 warm start
+  HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int> p32(B), it32(B);
+  for (int b = 0; b < B; ++b) {
+    const SolveCtl& C = pl->ctl_host[b];
+    launch_convert<double>(n3, w32.U + ((size_t)C.result * B + b) * n3, 1, pl->U + (size_t)b * n3, s);
+    p32[b] = C.passes;
+    it32[b] = C.iters;
+  }
+  LAUNCHCHK();
+  Ws<double> w = ws64(pl);
+  TRY(setup_source<double>(pl, p, delta, w, false, s));
+  launch_absmean<double>(n3, w.S, B, pl->red, pl->vec, nullptr, s);
+  launch_ctl_init(pl->ctl, pl->vec, B, s);
+  launch_p1_fwd<double>(pl->n, w.U, w.spec_u, B, nullptr, s);
+  const int left = std::max(0, p->max_iter - *std::min_element(it32.begin(), it32.end()));
+  SolveCfg cfg = solve_cfg(pl, p, p->tol, left);
+  int passes = 0;
+  TRY(run_loop<double>(pl, p, w, cfg, s, &passes));
+  const int st = collect<double>(pl, w, u_state, info, -1, s);
+  if (st < 0) return st;
+  if (info) {
+    for (int b = 0; b < B; ++b) {
+      info[b].passes_fp64 = info[b].passes;
+      info[b].passes += p32[b];
+      info[b].iters += it32[b];
+    }
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------ PM
+static int require_batch1(const dgp_plan* pl) {
+  if (pl->batch != 1) return fail(DGP_E_UNSUPPORTED, "particle entry points need a batch-1 plan");
+  return DGP_OK;
+}
+
+static int deposit_impl(dgp_plan* pl, const void* pos, int fp32, long long np, long long* grid, double* delta,
+                        bool remove_mean, hipStream_t s) {
+  Timed tm(pl, s, DGP_T_DEPOSIT);
+  HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
+  launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
+  if (delta) {
+    launch_counts_to_delta(pl->n, grid, np, delta, s);
+    if (remove_mean) {
+      launch_absmean<double>(pl->n3, delta, 1, pl->red, nullptr, pl->vec, s);
+      launch_sub_mean(pl->n3, delta, 1, pl->vec, s);
+    }
+  }
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+extern "C" int dgp_deposit(dgp_plan* pl, const void* pos, int pos_is_fp32, long long np, long long* grid_fixed,
+                           double* delta, void* stream) {
+  if (!pl || !pos || np < 1) return fail(DGP_E_INVALID, "plan, pos and np >= 1 are required");
+  TRY(require_batch1(pl));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TRY(deposit_impl(pl, pos, pos_is_fp32, np, grid_fixed ? grid_fixed : pl->grid, delta, true, s));
+  if (!grid_fixed && !delta) return DGP_OK;
+  return DGP_OK;
+}
+
+// force mesh g = -(c/H0)^2 grad phi, [3][n3] into mesh3 (and phi into phi_n when given)
+static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u, double* mesh3,
+                      double* phi_n, hipStream_t s) {
+  Timed tm(pl, s, DGP_T_FORCES);
+  const int n = pl->n;
+  const size_t fs = pl->hs;
+  SpecCoef cf = spec_coef(pl, p);
+  cf.with_phi = phi_n ? 1 : 0;
+  const bool use_u = p->force_mode == DGP_FORCE_NLDGP;
+  launch_p1_fwd<double>(n, delta, pl->spec6, 1, nullptr, s);
+  if (use_u) launch_p1_fwd<double>(n, u, pl->spec6 + fs, 1, nullptr, s);
+  launch_p2<double>(n, pl->spec6, use_u ? 2 : 1, 1, -1, nullptr, s);
+  const int nout = phi_n ? 4 : 3;
+  launch_p3<double>(n, SPEC_FORCES, pl->spec6, fs, use_u ? 2 : 1, pl->spec6 + 2 * fs, fs, nout, 1, cf, nullptr,
+                    nullptr, nullptr, nullptr, s);
+  launch_p2<double>(n, pl->spec6 + 2 * fs, nout, 1, +1, nullptr, s);
+  for (int d = 0; d < 3; ++d) launch_p1_inv<double>(n, pl->spec6 + (2 + d) * fs, mesh3 + d * pl->n3, 1, nullptr, s);
+  if (phi_n) launch_p1_inv<double>(n, pl->spec6 + 5 * fs, phi_n, 1, nullptr, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+extern "C" int dgp_pm_forces(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_state,
+                             const void* pos, int pos_is_fp32, long long np, double* force, double* phi_n,
+                             void* stream) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  TRY(check_params(p));
+  TRY(require_batch1(pl));
+  if (!delta || !pos || !force || np < 1) return fail(DGP_E_INVALID, "delta, pos, force and np >= 1 are required");
+  if (p->force_mode == DGP_FORCE_NLDGP && !u_state) return fail(DGP_E_INVALID, "u_state is required for nlDGP forces");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TRY(force_mesh(pl, p, delta, u_state, pl->mesh3, phi_n, s));
+  launch_interp(pl->n, pl->box, pl->mesh3, pos, pos_is_fp32, np, force, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel, int is_fp32, long long np, double dlna,
+                        double* u_state, dgp_info* info, void* stream) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  TRY(check_params(p));
+  TRY(require_batch1(pl));
+  if (!pos || !vel || !u_state || np < 1) return fail(DGP_E_INVALID, "pos, vel, u_state and np >= 1 are required");
+  if (!std::isfinite(dlna)) return fail(DGP_E_INVALID, "dlna must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TRY(deposit_impl(pl, pos, is_fp32, np, pl->grid, pl->delta, false, s));
+  int st = DGP_OK;
+  if (p->force_mode == DGP_FORCE_NLDGP) {
+    st = dgp_solve_field(pl, p, pl->delta, u_state, nullptr, info, stream);
+    if (st < 0) return st;
+  }
+  TRY(force_mesh(pl, p, pl->delta, u_state, pl->mesh3, nullptr, s));
+  const double a = p->a;
+  const double e_n = hubble_E(p->omega_m0, a);
+  const double a_h = a * std::exp(0.5 * dlna);
+  const double e_h = hubble_E(p->omega_m0, a_h);
+  const double kick = dlna / e_n;
+  const double drift = dlna / (a_h * a_h * e_h);
+  {
+    Timed tm(pl, s, DGP_T_INTERP_KICK);
+    launch_interp_kick_drift(pl->n, pl->box, pl->mesh3, pos, vel, is_fp32, np, kick, drift, s);
+  }
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  timing_flush(pl);
+  return st;
+}
+
+extern "C" int dgp_deposit_backward(dgp_plan* pl, const void* pos, int pos_is_fp32, long long np,
+                                    const double* grad_delta, double* grad_pos, void* stream) {
+  if (!pl || !pos || !grad_delta || !grad_pos || np < 1) return fail(DGP_E_INVALID, "missing argument");
+  TRY(require_batch1(pl));
+  launch_deposit_backward(pl->n, pl->box, pos, pos_is_fp32, np, grad_delta, grad_pos, static_cast<hipStream_t>(stream));
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+// ------------------------------------------------------------------ power spectrum
+static void bin_thresholds(int n, int nbins, std::vector<double>& t) {
+  t.resize(nbins + 1);
+  const double half = n / 2;
+  for (int b = 0; b <= nbins; ++b) t[b] = std::ceil(std::pow(half, 2.0 * b / nbins));
+  t[nbins] = half * half + 1.0;
+}
+
+static int power_impl(dgp_plan* pl, const dgp_params* p, const double* field, int of_c, int nbins,
+                      std::vector<double>& sums, std::vector<double>& cnts, hipStream_t s) {
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  std::vector<double> thr;
+  bin_thresholds(n, nbins, thr);
+  HIPCHK(hipMemcpyAsync(pl->bin_tab, thr.data(), sizeof(double) * thr.size(), hipMemcpyHostToDevice, s));
+  SpecCoef cf = spec_coef(pl, p);
+  cf.nbins = nbins;
+  cf.power_c = of_c ? 1 : 0;
+  TRY(fwd3<double>(pl, field, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_POWER, pl->spec_u, fs, 1, nullptr, 0, 0, B, cf, pl->bin_tab, pl->bin_partial, nullptr,
+                    nullptr, s);
+  LAUNCHCHK();
+  const int g = p3_row_groups(n);
+  const size_t cnt = (size_t)B * g * 2 * nbins;
+  HIPCHK(hipMemcpyAsync(pl->bin_host, pl->bin_partial, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  sums.assign((size_t)B * nbins, 0.0);
+  cnts.assign((size_t)B * nbins, 0.0);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < g; ++k) {
+      const double* row = pl->bin_host + ((size_t)b * g + k) * 2 * nbins;
+      for (int i = 0; i < nbins; ++i) {
+        sums[(size_t)b * nbins + i] += row[i];
+        cnts[(size_t)b * nbins + i] += row[nbins + i];
+      }
+    }
+  return DGP_OK;
+}
+
+extern "C" int dgp_power_spectrum(dgp_plan* pl, const dgp_params* p, const double* field, int of_c, int nbins,
+                                  double* pk, double* counts, void* stream) {
+  if (!pl || !field || !pk) return fail(DGP_E_INVALID, "missing argument");
+  TRY(check_params(p));
+  if (nbins < 1 || nbins > 128) return fail(DGP_E_INVALID, "nbins must be in [1, 128]");
+  std::vector<double> sums, cnts;
+  TRY(power_impl(pl, p, field, of_c, nbins, sums, cnts, static_cast<hipStream_t>(stream)));
+  const double norm = std::pow(pl->box, 3) / (double(pl->n3) * double(pl->n3));
+  for (int b = 0; b < pl->batch; ++b)
+    for (int i = 0; i < nbins; ++i) {
+      const double c = cnts[(size_t)b * nbins + i];
+      pk[(size_t)b * nbins + i] = c > 0 ? sums[(size_t)b * nbins + i] / c * norm : 0.0;
+    }
+  if (counts)
+    for (int i = 0; i < nbins; ++i) counts[i] = cnts[i];
+  return DGP_OK;
+}
+
+extern "C" int dgp_power_spectrum_backward(dgp_plan* pl, const dgp_params* p, const double* field, int of_c,
+                                           int nbins, const double* grad_pk, double* grad_field, void* stream) {
+  if (!pl || !field || !grad_pk || !grad_field) return fail(DGP_E_INVALID, "missing argument");
+  TRY(check_params(p));
+  if (nbins < 1 || nbins > 128) return fail(DGP_E_INVALID, "nbins must be in [1, 128]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<double> sums, cnts;
+  TRY(power_impl(pl, p, field, of_c, nbins, sums, cnts, s));
+  const int n = pl->n, B = pl->batch;
+  std::vector<double> tab;
+  bin_thresholds(n, nbins, tab);
+  const double norm = std::pow(pl->box, 3) / (double(pl->n3) * double(pl->n3));
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < nbins; ++i) {
+      const double c = cnts[(size_t)b * nbins + i];
+      tab.push_back(c > 0 ? grad_pk[(size_t)b * nbins + i] * norm / c * 2.0 * double(pl->n3) : 0.0);
+    }
+  HIPCHK(hipMemcpyAsync(pl->bin_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, s));
+  SpecCoef cf = spec_coef(pl, p);
+  cf.nbins = nbins;
+  cf.power_c = of_c ? 1 : 0;
+  const size_t fs = (size_t)B * pl->hs;
+  TRY(fwd3<double>(pl, field, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_POWER_GRAD, pl->spec_u, fs, 1, pl->spec6, fs, 1, B, cf, pl->bin_tab, nullptr, nullptr,
+                    nullptr, s);
+  launch_p2<double>(n, pl->spec6, 1, B, +1, nullptr, s);
+  launch_p1_inv<double>(n, pl->spec6, grad_field, B, nullptr, s);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  return DGP_OK;
+}
+
+// ------------------------------------------------------------------ raw transforms (tests of the FFT itself)
+extern "C" int dgp_fft_forward(dgp_plan* pl, const double* field, double* spectrum, void* stream) {
+  if (!pl || !field || !spectrum) return fail(DGP_E_INVALID, "missing argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  dgp_params p;
+  dgp_params_init(&p, 0.27, 1.0);
+  const SpecCoef cf = spec_coef(pl, &p);
+  if (pl->precision == DGP_FP64) {
+    TRY(fwd3<double>(pl, field, pl->spec_u, B, nullptr, s));
+    launch_p3<double>(n, SPEC_FWD_ONLY, pl->spec_u, fs, 1, reinterpret_cast<cx<double>*>(spectrum), fs, 1, B, cf,
+                      nullptr, nullptr, nullptr, nullptr, s);
+  } else {
+    launch_convert<float>(B * pl->n3, field, 0, pl->U32, s);
+    TRY(fwd3<float>(pl, pl->U32, pl->spec_u32, B, nullptr, s));
+    launch_p3<float>(n, SPEC_FWD_ONLY, pl->spec_u32, fs, 1, pl->spec6_32, fs, 1, B, cf, nullptr, nullptr, nullptr,
+                     nullptr, s);
+    launch_convert<double>(2 * fs, pl->spec6_32, 1, spectrum, s);
+  }
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+extern "C" int dgp_fft_inverse(dgp_plan* pl, const double* spectrum, double* field, void* stream) {
+  if (!pl || !field || !spectrum) return fail(DGP_E_INVALID, "missing argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs;
+  dgp_params p;
+  dgp_params_init(&p, 0.27, 1.0);
+  const SpecCoef cf = spec_coef(pl, &p);
+  if (pl->precision == DGP_FP64) {
+    launch_p3<double>(n, SPEC_INV_ONLY, reinterpret_cast<const cx<double>*>(spectrum), fs, 1, pl->spec_u, fs, 1, B, cf,
+                      nullptr, nullptr, nullptr, nullptr, s);
+    launch_p2<double>(n, pl->spec_u, 1, B, +1, nullptr, s);
+    launch_p1_inv<double>(n, pl->spec_u, field, B, nullptr, s);
+  } else {
+    launch_convert<float>(2 * fs, spectrum, 0, reinterpret_cast<float*>(pl->spec6_32), s);
+    launch_p3<float>(n, SPEC_INV_ONLY, pl->spec6_32, fs, 1, pl->spec_u32, fs, 1, B, cf, nullptr, nullptr, nullptr,
+                     nullptr, s);
+    launch_p2<float>(n, pl->spec_u32, 1, B, +1, nullptr, s);
+    launch_p1_inv<float>(n, pl->spec_u32, pl->U32, B, nullptr, s);
+    launch_convert<double>(B * pl->n3, pl->U32, 1, field, s);
+  }
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star, const double* grad_u,
+                  double* grad_delta, dgp_info* info, hipStream_t s);
+
+extern "C" int dgp_solve_field_backward(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star,
+                                        const double* grad_u, double* grad_delta, dgp_info* info, void* stream) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  TRY(check_params(p));
+  if (!delta || !u_star || !grad_u || !grad_delta) return fail(DGP_E_INVALID, "missing argument");
+  return adjoint_solve(pl, p, delta, u_star, grad_u, grad_delta, info, static_cast<hipStream_t>(stream));
+}
+
+int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star, const double* grad_u,
+                  double* grad_delta, dgp_info* info, hipStream_t s) {
+  (void)pl; (void)p; (void)delta; (void)u_star; (void)grad_u; (void)grad_delta; (void)info; (void)s;
+  return fail(DGP_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+// ------------------------------------------------------------------ live kernel timing
+extern "C" int dgp_timing_enable(dgp_plan* pl, int on) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  timing_flush(pl);
+  pl->timing = on != 0;
+  for (int i = 0; i < DGP_T_NCLASS; ++i) {
+    pl->t_ms[i] = 0.0;
+    pl->t_cnt[i] = 0;
+  }
+  return DGP_OK;
+}
+
+extern "C" int dgp_timing_read(dgp_plan* pl, int cls, double* total_ms, long long* launches) {
+  if (!pl || cls < 0 || cls >= DGP_T_NCLASS) return fail(DGP_E_INVALID, "bad timing class");
+  timing_flush(pl);
+  if (total_ms) *total_ms = pl->t_ms[cls];
+  if (launches) *launches = pl->t_cnt[cls];
+  return DGP_OK;
+}

@@ -1,0 +1,153 @@
+// Internal declarations shared by the libdgp translation units (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "fft_engine.h"
+
+namespace dgp {
+
+// Spectral multiplier modes of the axis-2 pass (forward FFT of each input row,
+// per-mode combination, inverse FFT of each output row).
+enum SpecMode : int {
+  SPEC_FANOUT6 = 0,   // u(k) -> 5 Hessian components (00,11,01,02,12) and sqrt(-lap)C = -u/kbar
+  SPEC_SOURCE = 1,    // delta(k) -> S(k) = A(1 - beta/kbar) delta, u_lin(k) = S/(alpha - gamma/kbar)
+  SPEC_CFIELD = 2,    // u(k) -> C(k) = -u/kbar^2
+  SPEC_FORCES = 3,    // delta(k)[, u(k)] -> g_i = -(c/H0)^2 i k_i phi(k), i = 0..2 [, phi(k)]
+  SPEC_POWER = 4,     // f(k) -> per-bin sums of |f|^2 (no outputs); optional 1/kbar^2 weight
+  SPEC_POWER_GRAD = 5,// f(k) -> per-bin coefficient * f(k) [* 1/kbar^4]
+  SPEC_ADJ_COMBINE = 6,// 6 inputs (products with mu) -> one combined spectrum
+  SPEC_COPY = 7,      // identity (plain forward+inverse round trip, for tests)
+  SPEC_FWD_ONLY = 8,  // forward axis-2 transform only (spectrum export)
+  SPEC_INV_ONLY = 9,  // inverse axis-2 transform only, times 1/N^3 (spectrum import)
+};
+
+enum ForceMode : int { FORCE_NLDGP = 0, FORCE_LDGP = 1, FORCE_GRH = 2 };
+
+// Coefficients consumed by the spectral kernels (all double; fp32 kernels round at use).
+struct SpecCoef {
+  double kf;        // 2 pi / L
+  double kappa;     // c/(aH) [Mpc/h]
+  double A, beta, alpha, gamma;   // effective (nonlocal terms zeroed when disabled)
+  double om15;      // (3/2)(eta-1)/eta
+  double inv2eta;   // 1/(2 eta)
+  double c2;        // coefficient of sqrt(-lap) C in the modified Poisson equation (0 if nonlocal off)
+  double inv_eta_nl;// 1/eta in the sqrt(-lap) phi term (0 if nonlocal off)
+  double force_scale;  // (c/H0)^2
+  double inv_n3;    // 1/N^3 (inverse-transform normalisation, folded into the multiplier)
+  double lam2;      // 2 lam (adjoint combine)
+  int force_mode;   // ForceMode
+  int with_phi;     // FORCES: also output phi
+  int power_c;      // POWER/POWER_GRAD: weight |f|^2 by 1/kbar^4 (spectrum of C from u)
+  int nbins;        // POWER: number of bins
+};
+
+// Per-batch-element control block of the relaxation (device memory).
+constexpr int kMaxHist = 256;
+struct SolveCtl {
+  int done;         // 1 once the returned iterate is decided
+  int status;       // 0 ok, 1 not converged (max_iter), 2 stopped at min residual with bad points
+  int iters;        // updates applied to the current iterate
+  int cur;          // buffer index holding u^(iters)
+  int out;          // buffer the next update writes
+  int best;         // buffer index of the minimum-residual iterate
+  int result;       // buffer index of the returned iterate
+  int bad_seen;
+  int passes;       // residual evaluations executed
+  int last_bad;     // bad points of the last update
+  double eps;       // <|S|>
+  double resid;     // r of the returned iterate
+  double resid_min;
+  double bad_frac;
+  double mean_u;    // <u> of the current iterate (from its k = 0 mode)
+  double hist[kMaxHist];
+};
+
+struct SolveCfg {
+  double lam, w, alpha, gamma, omega, tol;
+  int max_iter;
+  int n;            // mesh size
+  int batch;
+};
+
+// Real-FFT tile geometry: complex "pair columns" per workgroup for the axis-0 passes.
+template <typename T, int N, int R>
+struct AxisTile {
+  static constexpr int kT = N / R;                                       // threads per transform
+  static constexpr int kBase = 128 / (2 * int(sizeof(T)) * 2);           // pairs for 128-B complex rows
+  static constexpr int kWant = (64 / kT > kBase) ? 64 / kT : kBase;
+  static constexpr int kTP = (kWant > N / 2) ? N / 2 : kWant;            // pairs per workgroup
+  static constexpr int kThreads = kTP * kT;
+};
+
+// Column tile of the axis-1 pass.
+template <typename T, int N, int R>
+struct ColTile {
+  static constexpr int kT = N / R;
+  static constexpr int kBase = 128 / int(sizeof(cx<T>));
+  static constexpr int kWant0 = (64 / kT > kBase) ? 64 / kT : kBase;
+  static constexpr int kCap = (512 / kT > 1) ? 512 / kT : 1;
+  static constexpr int kWant = (kWant0 > kCap) ? kCap : kWant0;
+  static constexpr int kTY = (kWant > N) ? N : kWant;
+  static constexpr int kThreads = kTY * kT;
+};
+
+// Row tile of the axis-2 pass.
+template <int N, int R>
+struct RowTile {
+  static constexpr int kT = N / R;
+  static constexpr int kRW = (256 / kT > 1) ? 256 / kT : 1;
+  static constexpr int kThreads = kRW * kT;
+};
+
+// ------------------------------------------------------------------ launchers
+// All launchers are asynchronous on `stream`; `done` (may be null) is a per-batch
+// flag array: work for a batch element whose flag is set is skipped.
+
+template <typename T>
+void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ctl, hipStream_t s);
+template <typename T>
+void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s);
+// nf fields, each [batch][H][N][N]; DIR -1 forward, +1 inverse
+template <typename T>
+void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, hipStream_t s);
+// axis-2 pass: nin input arrays (each [batch][H][N][N]) -> nout output arrays
+template <typename T>
+void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out,
+               size_t out_stride, int nout, int batch, const SpecCoef& coef, const double* bin_coef,
+               double* bin_partial, double* mean_out, const SolveCtl* ctl, hipStream_t s);
+int p3_row_groups(int n);   // workgroups per batch element of the axis-2 pass (for POWER partials)
+
+// fused relaxation pass (inverse axis-0 of 6 spectra + pointwise update + forward axis-0)
+template <typename T>
+void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* s_field, cx<T>* spec_u, double* partial,
+                  const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s);
+int relax_groups(int n, int elem_bytes);   // workgroups per batch element of the fused pass
+
+void launch_finalize(const double* partial, int groups, SolveCtl* ctl, const SolveCfg& cfg,
+                     int* n_active, hipStream_t s);
+
+// reductions: per-batch mean of |x| and mean of x (double results)
+template <typename T>
+void launch_absmean(size_t n3, const T* x, int batch, double* scratch, double* abs_mean, double* mean,
+                    hipStream_t s);
+size_t absmean_scratch_doubles(size_t n3, int batch);
+// control blocks: eps from abs_mean[b], buffer roles reset
+void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s);
+
+// PM kernels
+void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
+                    hipStream_t s);
+void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s);
+void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
+void launch_interp(int n, double box, const double* mesh3, const void* pos, int pos_fp32, long long np,
+                   double* force, hipStream_t s);
+void launch_interp_kick_drift(int n, double box, const double* mesh3, void* pos, void* vel, int fp32,
+                              long long np, double kick, double drift, hipStream_t s);
+void launch_deposit_backward(int n, double box, const void* pos, int pos_fp32, long long np,
+                             const double* grad_delta, double* grad_pos, hipStream_t s);
+template <typename T>
+void launch_convert(size_t count, const void* in, int in_fp32, T* out, hipStream_t s);
+
+}  // namespace dgp

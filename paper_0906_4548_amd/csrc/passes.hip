@@ -1,0 +1,484 @@
+// Axis passes of the 3D real FFT on the periodic mesh, and the spectral multipliers.
+//
+// Layouts (C order, last index fastest):
+//   real field      [batch][N][N][N]          index (i0, i1, i2)
+//   spectrum        [batch][N/2+1][N][N]      complex, index (k0, k1, k2)
+// The real-to-complex step runs along axis 0 (the slowest), so the half axis is
+// k0 and every pass moves whole N x N planes: no odd-sized inner dimension.
+//   axis-0 pass (p1): strided columns, two real columns packed as one complex
+//                     transform (x_a + i x_b), separated with Hermitian symmetry;
+//   axis-1 pass (p2): strided complex columns, tiles of 128-byte row segments;
+//   axis-2 pass (p3): contiguous complex rows; forward transform, spectral
+//                     multipliers, inverse transforms of every output.
+// Forward transforms are unnormalised; the 1/N^3 of the inverse is folded into
+// the spectral multipliers (numpy convention).
+//
+// Spectral conventions (the Fourier-space operators of Sec. II and III B):
+//   k_d = kf * n_d with signed mode numbers n_d in [-N/2, N/2); kbar = kappa |k|;
+//   k = 0 multipliers of 1/kbar, 1/k^2, k_i k_j / k^2 are 0; a multiplier odd in
+//   component d (mixed Hessian terms, the gradient) is 0 at the Nyquist index of d.
+#include "dgp_internal.h"
+
+namespace dgp {
+
+// radix plan and workgroup shapes of each pass, per element type and mesh size
+template <typename T, int N>
+struct Geo {
+  using P = Plan8<N>;
+  static constexpr int R = P::R;
+  static constexpr int kP1 = AxisTile<T, N, R>::kThreads;
+  static constexpr int kP2 = ColTile<T, N, R>::kThreads;
+  static constexpr int kP3 = RowTile<N, R>::kThreads;
+};
+
+__device__ __forceinline__ bool batch_done(const SolveCtl* ctl, int b) {
+  return ctl != nullptr && ctl[b].done != 0;
+}
+
+// ------------------------------------------------------------------ axis 0, forward (real -> complex)
+template <typename T, int N>
+__global__ void __launch_bounds__((Geo<T, N>::kP1))
+k_p1_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+         const SolveCtl* __restrict__ ctl) {
+  using P = typename Geo<T, N>::P;
+  constexpr int R = P::R;
+  using G = AxisTile<T, N, R>;
+  constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
+  const int b = blockIdx.z;
+  if (batch_done(ctl, b)) return;
+  const int i1 = blockIdx.y;
+  const int c = threadIdx.x % TP, t = threadIdx.x / TP;
+  const int i2 = (blockIdx.x * TP + c) * 2;
+  __shared__ cx<T> lds[N * TP];
+  const T* src = in + (size_t)b * N * N * N + (size_t)i1 * N + i2;
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = *reinterpret_cast<const cx<T>*>(src + (size_t)(t + q * TT) * N * N);
+  LdsCol<T, TP> L{lds, c};
+  fft<T, N, P, -1>(v, tw, L, t);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
+  __syncthreads();
+  cx<T>* dst = out + (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  for (int k = t; k < H; k += TT) {
+    const cx<T> zk = lds[k * TP + c];
+    const cx<T> zn = lds[((N - k) & (N - 1)) * TP + c];
+    // x_a(k) = (Z(k) + conj Z(N-k)) / 2,  x_b(k) = (Z(k) - conj Z(N-k)) / (2i)
+    const cx<T> xa = mk(T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y));
+    const cx<T> xb = mk(T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x));
+    dst[(size_t)k * N * N] = xa;
+    dst[(size_t)k * N * N + 1] = xb;
+  }
+}
+
+// ------------------------------------------------------------------ axis 0, inverse (complex -> real)
+template <typename T, int N>
+__global__ void __launch_bounds__((Geo<T, N>::kP1))
+k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
+         const SolveCtl* __restrict__ ctl) {
+  using P = typename Geo<T, N>::P;
+  constexpr int R = P::R;
+  using G = AxisTile<T, N, R>;
+  constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
+  constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
+  const int b = blockIdx.z;
+  if (batch_done(ctl, b)) return;
+  const int i1 = blockIdx.y;
+  const int c = threadIdx.x % TP, t = threadIdx.x / TP;
+  const int i2 = (blockIdx.x * TP + c) * 2;
+  __shared__ cx<T> lds[LSZ];
+  const cx<T>* src = in + (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  for (int k = t; k < H; k += TT) {
+    lds[k * 2 * TP + 2 * c] = src[(size_t)k * N * N];
+    lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
+  }
+  __syncthreads();
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int e = t + q * TT;
+    cx<T> xa, xb;
+    if (e <= N / 2) {
+      xa = lds[e * 2 * TP + 2 * c];
+      xb = lds[e * 2 * TP + 2 * c + 1];
+      if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
+    } else {
+      xa = conjg(lds[(N - e) * 2 * TP + 2 * c]);
+      xb = conjg(lds[(N - e) * 2 * TP + 2 * c + 1]);
+    }
+    v[q] = mk(xa.x - xb.y, xa.y + xb.x);   // x_a + i x_b
+  }
+  LdsCol<T, TP> L{lds, c};
+  fft<T, N, P, +1>(v, tw, L, t);
+  T* dst = out + (size_t)b * N * N * N + (size_t)i1 * N + i2;
+#pragma unroll
+  for (int q = 0; q < R; ++q) *reinterpret_cast<cx<T>*>(dst + (size_t)(t + q * TT) * N * N) = v[q];
+}
+
+// ------------------------------------------------------------------ axis 1 (strided complex columns, in place)
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__((Geo<T, N>::kP2))
+k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const SolveCtl* __restrict__ ctl) {
+  using P = typename Geo<T, N>::P;
+  constexpr int R = P::R;
+  using G = ColTile<T, N, R>;
+  constexpr int TY = G::kTY, TT = G::kT, H = N / 2 + 1;
+  const int fb = blockIdx.z;
+  if (batch_done(ctl, fb % batch)) return;
+  const int k0 = blockIdx.y;
+  const int c = threadIdx.x % TY, t = threadIdx.x / TY;
+  __shared__ cx<T> lds[N * TY];
+  cx<T>* base = data + ((size_t)fb * H + k0) * N * N + blockIdx.x * TY + c;
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = base[(size_t)(t + q * TT) * N];
+  LdsCol<T, TY> L{lds, c};
+  fft<T, N, P, DIR>(v, tw, L, t);
+#pragma unroll
+  for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
+}
+
+// ------------------------------------------------------------------ axis 2 with spectral multipliers
+struct Mode3 {
+  int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
+  bool q0, q1, q2;       // Nyquist flags
+  long long msq;         // |n|^2
+};
+
+__device__ __forceinline__ Mode3 mode_of(int N, int k0, int k1, int k2) {
+  Mode3 m;
+  m.n0 = k0;
+  m.n1 = (k1 < N / 2) ? k1 : k1 - N;
+  m.n2 = (k2 < N / 2) ? k2 : k2 - N;
+  m.q0 = (k0 == N / 2);
+  m.q1 = (k1 == N / 2);
+  m.q2 = (k2 == N / 2);
+  m.msq = (long long)m.n0 * m.n0 + (long long)m.n1 * m.n1 + (long long)m.n2 * m.n2;
+  return m;
+}
+
+template <typename T, int N, SpecMode MODE>
+__global__ void __launch_bounds__((Geo<T, N>::kP3))
+k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, size_t out_stride,
+     const cx<T>* __restrict__ tw, SpecCoef cf, const double* __restrict__ bin_coef,
+     double* __restrict__ bin_partial, double* __restrict__ mean_out, const SolveCtl* __restrict__ ctl) {
+  using P = typename Geo<T, N>::P;
+  constexpr int R = P::R;
+  using G = RowTile<N, R>;
+  constexpr int RW = G::kRW, TT = G::kT, H = N / 2 + 1;
+  constexpr int ROWS = H * N;
+  const int b = blockIdx.y;
+  if (batch_done(ctl, b)) return;
+  const int t = threadIdx.x % TT, c = threadIdx.x / TT;
+  const int row = blockIdx.x * RW + c;
+  const bool valid = row < ROWS;
+  const int rr = valid ? row : 0;
+  const int k0 = rr / N, k1 = rr % N;
+  __shared__ cx<T> lds[RW * (N + N / 16)];
+  LdsRow<T, N> L{lds, c};
+  const size_t roff = (size_t)b * ROWS * N + (size_t)rr * N;
+
+  cx<T> v[R];
+  auto load_row = [&](const cx<T>* src) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = valid ? src[roff + t + q * TT] : mk(T(0), T(0));
+  };
+  auto store_row = [&](cx<T>* dst, cx<T> (&w)[R]) {
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[roff + t + q * TT] = w[q];
+    }
+  };
+  const double kf = cf.kf;
+
+  if constexpr (MODE == SPEC_FWD_ONLY || MODE == SPEC_INV_ONLY) {
+    load_row(in);
+    if constexpr (MODE == SPEC_FWD_ONLY) {
+      fft<T, N, P, -1>(v, tw, L, t);
+    } else {
+      fft<T, N, P, +1>(v, tw, L, t);
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = scale(v[q], T(cf.inv_n3));
+    }
+    store_row(out, v);
+    return;
+  } else if constexpr (MODE == SPEC_POWER) {
+    __shared__ double bins[2 * 128];
+    for (int i = threadIdx.x; i < 2 * cf.nbins; i += blockDim.x) bins[i] = 0.0;
+    load_row(in);
+    fft<T, N, P, -1>(v, tw, L, t);
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        const double ms = double(m.msq);
+        if (ms >= bin_coef[0] && ms < bin_coef[cf.nbins]) {
+          int lo = 0, hi = cf.nbins;   // largest lo with thr[lo] <= ms
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bin_coef[mid] <= ms) lo = mid; else hi = mid;
+          }
+          const double mult = (m.n0 == 0 || m.q0) ? 1.0 : 2.0;
+          double p2 = double(v[q].x) * double(v[q].x) + double(v[q].y) * double(v[q].y);
+          if (cf.power_c) {
+            const double kb2 = cf.kappa * cf.kappa * kf * kf * ms;
+            p2 /= kb2 * kb2;
+          }
+          atomicAdd(&bins[lo], mult * p2);
+          atomicAdd(&bins[cf.nbins + lo], mult);
+        }
+      }
+    }
+    __syncthreads();
+    double* dstp = bin_partial + ((size_t)b * gridDim.x + blockIdx.x) * 2 * cf.nbins;
+    for (int i = threadIdx.x; i < 2 * cf.nbins; i += blockDim.x) dstp[i] = bins[i];
+    return;
+  } else if constexpr (MODE == SPEC_ADJ_COMBINE) {
+    cx<T> acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = mk(T(0), T(0));
+#pragma unroll 1
+    for (int f = 0; f < 6; ++f) {
+      load_row(in + f * in_stride);
+      fft<T, N, P, -1>(v, tw, L, t);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        if (m.msq == 0) continue;
+        const double ik2 = 1.0 / double(m.msq);
+        double mult;
+        if (f == 0) mult = cf.lam2 * double(m.n0) * double(m.n0) * ik2;
+        else if (f == 1) mult = cf.lam2 * double(m.n1) * double(m.n1) * ik2;
+        else if (f == 2) mult = (m.q0 || m.q1) ? 0.0 : 2.0 * cf.lam2 * double(m.n0) * double(m.n1) * ik2;
+        else if (f == 3) mult = (m.q0 || m.q2) ? 0.0 : 2.0 * cf.lam2 * double(m.n0) * double(m.n2) * ik2;
+        else if (f == 4) mult = (m.q1 || m.q2) ? 0.0 : 2.0 * cf.lam2 * double(m.n1) * double(m.n2) * ik2;
+        else mult = cf.gamma / (cf.kappa * kf * sqrt(double(m.msq)));
+        const T mm = T(mult * cf.inv_n3);
+        acc[q] = acc[q] + scale(v[q], mm);
+      }
+    }
+    fft<T, N, P, +1>(acc, tw, L, t);
+    store_row(out, acc);
+    return;
+  } else {
+    // single-input or two-input modes
+    load_row(in);
+    fft<T, N, P, -1>(v, tw, L, t);
+    cx<T> v2[(MODE == SPEC_FORCES) ? R : 1];
+    if constexpr (MODE == SPEC_FORCES) {
+      if (cf.force_mode == FORCE_NLDGP) {
+        cx<T> keep[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) keep[q] = v[q];
+        load_row(in + in_stride);
+        fft<T, N, P, -1>(v, tw, L, t);
+#pragma unroll
+        for (int q = 0; q < R; ++q) { v2[q] = v[q]; v[q] = keep[q]; }
+      }
+    }
+    if constexpr (MODE == SPEC_FANOUT6) {
+      if (valid && k0 == 0 && k1 == 0 && t == 0 && mean_out != nullptr) mean_out[b] = double(v[0].x) * cf.inv_n3;
+    }
+    constexpr int NOUT = (MODE == SPEC_FANOUT6) ? 6 : (MODE == SPEC_SOURCE) ? 2 : (MODE == SPEC_FORCES) ? 4 : 1;
+#pragma unroll 1
+    for (int o = 0; o < NOUT; ++o) {
+      if constexpr (MODE == SPEC_FORCES) {
+        if (o == 3 && !cf.with_phi) break;
+      }
+      cx<T> w[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        const double ms = double(m.msq);
+        cx<T> res = mk(T(0), T(0));
+        if (m.msq != 0) {
+          const double ik2 = 1.0 / ms;
+          const double kb = cf.kappa * kf * sqrt(ms);
+          const double ikb = 1.0 / kb;
+          if constexpr (MODE == SPEC_FANOUT6) {
+            double mult;
+            if (o == 0) mult = double(m.n0) * double(m.n0) * ik2;
+            else if (o == 1) mult = double(m.n1) * double(m.n1) * ik2;
+            else if (o == 2) mult = (m.q0 || m.q1) ? 0.0 : double(m.n0) * double(m.n1) * ik2;
+            else if (o == 3) mult = (m.q0 || m.q2) ? 0.0 : double(m.n0) * double(m.n2) * ik2;
+            else if (o == 4) mult = (m.q1 || m.q2) ? 0.0 : double(m.n1) * double(m.n2) * ik2;
+            else mult = -ikb;
+            res = scale(v[q], T(mult * cf.inv_n3));
+          } else if constexpr (MODE == SPEC_SOURCE) {
+            const double s = cf.A * (1.0 - cf.beta * ikb);
+            const double mult = (o == 0) ? s : s / (cf.alpha - cf.gamma * ikb);
+            res = scale(v[q], T(mult * cf.inv_n3));
+          } else if constexpr (MODE == SPEC_CFIELD) {
+            res = scale(v[q], T(-ikb * ikb * cf.inv_n3));
+          } else if constexpr (MODE == SPEC_COPY) {
+            res = scale(v[q], T(cf.inv_n3));
+          } else if constexpr (MODE == SPEC_POWER_GRAD) {
+            double coef = 0.0;
+            const double* thr = bin_coef;
+            if (ms >= thr[0] && ms < thr[cf.nbins]) {
+              int lo = 0, hi = cf.nbins;
+              while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (thr[mid] <= ms) lo = mid; else hi = mid;
+              }
+              coef = thr[cf.nbins + 1 + (size_t)b * cf.nbins + lo];
+              if (cf.power_c) coef *= (ikb * ikb) * (ikb * ikb);
+            }
+            res = scale(v[q], T(coef * cf.inv_n3));
+          } else if constexpr (MODE == SPEC_FORCES) {
+            // phi(k) from the modified Poisson equation (or its linear / GR forms)
+            const double dr = double(v[q].x), di = double(v[q].y);
+            double nr, ni, den;
+            if (cf.force_mode == FORCE_GRH) {
+              nr = cf.om15 * dr; ni = cf.om15 * di; den = kb * kb;
+            } else {
+              double ur, ui;
+              if (cf.force_mode == FORCE_NLDGP) {
+                ur = double(v2[q].x); ui = double(v2[q].y);
+              } else {   // linear solution from delta
+                const double s = cf.A * (1.0 - cf.beta * ikb) / (cf.alpha - cf.gamma * ikb);
+                ur = s * dr; ui = s * di;
+              }
+              const double cu = -cf.inv2eta + cf.c2 * ikb;
+              nr = cf.om15 * dr + cu * ur;
+              ni = cf.om15 * di + cu * ui;
+              den = kb * kb + kb * cf.inv_eta_nl;
+            }
+            const double pr = -nr / den, pi = -ni / den;
+            if (o < 3) {
+              const int nd = (o == 0) ? m.n0 : (o == 1) ? m.n1 : m.n2;
+              const bool nq = (o == 0) ? m.q0 : (o == 1) ? m.q1 : m.q2;
+              const double kd = nq ? 0.0 : kf * double(nd);
+              // g = -(c/H0)^2 (i k_d) phi
+              const double sc = -cf.force_scale * kd * cf.inv_n3;
+              res = mk(T(-sc * pi), T(sc * pr));
+            } else {
+              res = mk(T(pr * cf.inv_n3), T(pi * cf.inv_n3));
+            }
+          }
+        }
+        w[q] = res;
+      }
+      fft<T, N, P, +1>(w, tw, L, t);
+      store_row(out + o * out_stride, w);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int N>
+static void p1_fwd_n(const T* in, cx<T>* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  using G = AxisTile<T, N, Geo<T, N>::R>;
+  dim3 grid(N / (2 * G::kTP), N, batch);
+  hipLaunchKernelGGL((k_p1_fwd<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
+}
+template <typename T, int N>
+static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  using G = AxisTile<T, N, Geo<T, N>::R>;
+  dim3 grid(N / (2 * G::kTP), N, batch);
+  hipLaunchKernelGGL((k_p1_inv<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
+}
+template <typename T, int N>
+static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  using G = ColTile<T, N, Geo<T, N>::R>;
+  dim3 grid(N / G::kTY, N / 2 + 1, nf * batch);
+  if (dir < 0) hipLaunchKernelGGL((k_p2<T, N, -1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);
+  else hipLaunchKernelGGL((k_p2<T, N, +1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);
+}
+template <typename T, int N>
+static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t os, int batch, const SpecCoef& cf,
+                 const double* bc, double* bp, double* mean, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  using G = RowTile<N, Geo<T, N>::R>;
+  constexpr int ROWS = (N / 2 + 1) * N;
+  dim3 grid((ROWS + G::kRW - 1) / G::kRW, batch);
+  dim3 blk(G::kThreads);
+#define DGP_P3(M) hipLaunchKernelGGL((k_p3<T, N, M>), grid, blk, 0, s, in, is, out, os, tw, cf, bc, bp, mean, ctl)
+  switch (mode) {
+    case SPEC_FANOUT6: DGP_P3(SPEC_FANOUT6); break;
+    case SPEC_SOURCE: DGP_P3(SPEC_SOURCE); break;
+    case SPEC_CFIELD: DGP_P3(SPEC_CFIELD); break;
+    case SPEC_FORCES: DGP_P3(SPEC_FORCES); break;
+    case SPEC_POWER: DGP_P3(SPEC_POWER); break;
+    case SPEC_POWER_GRAD: DGP_P3(SPEC_POWER_GRAD); break;
+    case SPEC_ADJ_COMBINE: DGP_P3(SPEC_ADJ_COMBINE); break;
+    case SPEC_COPY: DGP_P3(SPEC_COPY); break;
+    case SPEC_FWD_ONLY: DGP_P3(SPEC_FWD_ONLY); break;
+    case SPEC_INV_ONLY: DGP_P3(SPEC_INV_ONLY); break;
+  }
+#undef DGP_P3
+}
+
+template <typename T>
+const cx<T>* twiddles(int n);   // defined in api.cpp: device table exp(-2 pi i m / n)
+
+#define DGP_DISPATCH_N(n, CALL)        \
+  switch (n) {                         \
+    case 8: CALL(8); break;            \
+    case 16: CALL(16); break;          \
+    case 32: CALL(32); break;          \
+    case 64: CALL(64); break;          \
+    case 128: CALL(128); break;        \
+    case 256: CALL(256); break;        \
+    case 512: CALL(512); break;        \
+    default: break;                    \
+  }
+
+template <typename T>
+void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ctl, hipStream_t s) {
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p1_fwd_n<T, NN>(in, out, batch, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+template <typename T>
+void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s) {
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p1_inv_n<T, NN>(in, out, batch, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+template <typename T>
+void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, hipStream_t s) {
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p2_n<T, NN>(data, nf, batch, dir, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+template <typename T>
+void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out, size_t out_stride,
+               int nout, int batch, const SpecCoef& coef, const double* bin_coef, double* bin_partial,
+               double* mean_out, const SolveCtl* ctl, hipStream_t s) {
+  (void)nin;
+  (void)nout;
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p3_n<T, NN>(mode, in, in_stride, out, out_stride, batch, coef, bin_coef, bin_partial, mean_out, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+
+int p3_row_groups(int n) {
+  int r = 0;
+#define C(NN)                                                          \
+  {                                                                    \
+    using G = RowTile<NN, Plan8<NN>::R>;                               \
+    r = ((NN / 2 + 1) * NN + G::kRW - 1) / G::kRW;                     \
+  }
+  DGP_DISPATCH_N(n, C)
+#undef C
+  return r;
+}
+
+template void launch_p1_fwd<double>(int, const double*, cx<double>*, int, const SolveCtl*, hipStream_t);
+template void launch_p1_fwd<float>(int, const float*, cx<float>*, int, const SolveCtl*, hipStream_t);
+template void launch_p1_inv<double>(int, const cx<double>*, double*, int, const SolveCtl*, hipStream_t);
+template void launch_p1_inv<float>(int, const cx<float>*, float*, int, const SolveCtl*, hipStream_t);
+template void launch_p2<double>(int, cx<double>*, int, int, int, const SolveCtl*, hipStream_t);
+template void launch_p2<float>(int, cx<float>*, int, int, int, const SolveCtl*, hipStream_t);
+template void launch_p3<double>(int, SpecMode, const cx<double>*, size_t, int, cx<double>*, size_t, int, int,
+                                const SpecCoef&, const double*, double*, double*, const SolveCtl*, hipStream_t);
+template void launch_p3<float>(int, SpecMode, const cx<float>*, size_t, int, cx<float>*, size_t, int, int,
+                               const SpecCoef&, const double*, double*, double*, const SolveCtl*, hipStream_t);
+
+}  // namespace dgp

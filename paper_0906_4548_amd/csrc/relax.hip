@@ -1,0 +1,380 @@
+// Fused FFT-relaxation pass and its device-side convergence control.
+//
+// One relaxation pass (Sec. III B, Eq. FFTrelax with the w-split of Sec. III C)
+// evaluates the residual of the current iterate u^(n) and produces u^(n+1).  The
+// kernel here is its last stage: for a tile of axis-0 columns it
+//   1. inverse-transforms along axis 0 the five Hessian spectra h00, h11, h01,
+//      h02, h12 and the nonlocal spectrum Nf = -u(k)/kbar (the other two axes
+//      were inverted by the preceding passes), accumulating in FP64 registers
+//      sum_ij h_ij^2 and h22 = (u - <u>) - h00 - h11 (the trace identity:
+//      h00 + h11 + h22 = u - <u>, exact on the mesh, saves a sixth transform);
+//   2. evaluates, per point, the residual R of Eq. FullDGP2, B' of Eq. Bwpara,
+//      the discriminant of Eq. nabla^2Cwpara and its + root in the stable form
+//      2 B'/(alpha + sqrt(Delta)); a negative discriminant is a bad point and
+//      takes the vertex -alpha/(2 (1-w) lam) (Sec. III C);
+//   3. writes u^(n+1) and immediately forward-transforms it along axis 0, so
+//      the next pass starts from its axis-0 spectrum;
+//   4. reduces sum |R| (FP64) and the bad-point count per workgroup.
+// A single-workgroup kernel then forms r = <|R|>/eps (Eq. normres) per batch
+// element and runs the stopping rules; kernels of later passes read the
+// per-element `done` flag and exit at once.
+#include "dgp_internal.h"
+
+namespace dgp {
+
+template <typename T>
+const cx<T>* twiddles(int n);
+
+template <typename T, int N>
+__global__ void __launch_bounds__((AxisTile<T, N, 8>::kThreads))
+k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
+        cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
+        const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
+  using P = Plan8<N>;
+  constexpr int R = P::R;
+  using G = AxisTile<T, N, R>;
+  constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
+  constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
+  constexpr size_t N3 = (size_t)N * N * N;
+  const int b = blockIdx.z;
+  if (ctl[b].done) return;
+  const int cur = ctl[b].cur, nxt = ctl[b].out;
+  const int i1 = blockIdx.y;
+  const int c = threadIdx.x % TP, t = threadIdx.x / TP;
+  const int i2 = (blockIdx.x * TP + c) * 2;
+  __shared__ cx<T> lds[LSZ];
+  __shared__ double red[G::kThreads];
+  __shared__ int redi[G::kThreads];
+  LdsCol<T, TP> L{lds, c};
+
+  cx<double> s2[R], h22[R];
+  cx<T> v[R];
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    const cx<T>* src = spec6 + f * fstride + (size_t)b * H * N * N + (size_t)i1 * N + i2;
+    __syncthreads();
+    for (int k = t; k < H; k += TT) {
+      lds[k * 2 * TP + 2 * c] = src[(size_t)k * N * N];
+      lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
+      cx<T> xa, xb;
+      if (e <= N / 2) {
+        xa = lds[e * 2 * TP + 2 * c];
+        xb = lds[e * 2 * TP + 2 * c + 1];
+        if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
+      } else {
+        xa = conjg(lds[(N - e) * 2 * TP + 2 * c]);
+        xb = conjg(lds[(N - e) * 2 * TP + 2 * c + 1]);
+      }
+      v[q] = mk(xa.x - xb.y, xa.y + xb.x);
+    }
+    fft<T, N, P, +1>(v, tw, L, t);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double hx = double(v[q].x), hy = double(v[q].y);
+      if (f == 0) {
+        s2[q] = mk(hx * hx, hy * hy);
+        h22[q] = mk(-hx, -hy);
+      } else if (f == 1) {
+        s2[q] = mk(s2[q].x + hx * hx, s2[q].y + hy * hy);
+        h22[q] = mk(h22[q].x - hx, h22[q].y - hy);
+      } else if (f < 5) {
+        s2[q] = mk(s2[q].x + 2.0 * hx * hx, s2[q].y + 2.0 * hy * hy);
+      }
+    }
+  }
+  // pointwise residual and update; v holds Nf
+  const double lam = cfg.lam, w = cfg.w, alpha = cfg.alpha, gamma = cfg.gamma, omega = cfg.omega;
+  const double mu = mean_u[b];
+  const double vertex = -alpha / (2.0 * (1.0 - w) * lam);
+  const double c4 = 4.0 * (1.0 - w) * lam;
+  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+  T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
+  double abs_r = 0.0;
+  int nbad = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const size_t off = (size_t)(t + q * TT) * N * N;
+    const cx<T> up = *reinterpret_cast<const cx<T>*>(uin + off);
+    const cx<T> spv = *reinterpret_cast<const cx<T>*>(sp + off);
+    double un[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double u = double(j ? up.y : up.x);
+      const double s = double(j ? spv.y : spv.x);
+      const double nf = double(j ? v[q].y : v[q].x);
+      const double hz = (j ? h22[q].y : h22[q].x) + (u - mu);
+      const double sh2 = (j ? s2[q].y : s2[q].x) + hz * hz;
+      const double res = lam * (u * u - sh2) + alpha * u + gamma * nf - s;
+      abs_r += fabs(res);
+      const double bp = lam * (sh2 - w * u * u) - gamma * nf + s;
+      const double disc = alpha * alpha + c4 * bp;
+      double x;
+      if (disc < 0.0) {
+        x = vertex;
+        ++nbad;
+      } else {
+        x = 2.0 * bp / (alpha + sqrt(disc));
+      }
+      if (omega != 1.0) x = (1.0 - omega) * u + omega * x;
+      un[j] = x;
+    }
+    const cx<T> o = mk(T(un[0]), T(un[1]));
+    *reinterpret_cast<cx<T>*>(uout + off) = o;
+    v[q] = o;
+  }
+  // forward axis-0 transform of u^(n+1)
+  fft<T, N, P, -1>(v, tw, L, t);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
+  red[threadIdx.x] = abs_r;
+  redi[threadIdx.x] = nbad;
+  __syncthreads();
+  cx<T>* dst = spec_u + (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  for (int k = t; k < H; k += TT) {
+    const cx<T> zk = lds[k * TP + c];
+    const cx<T> zn = lds[((N - k) & (N - 1)) * TP + c];
+    dst[(size_t)k * N * N] = mk(T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y));
+    dst[(size_t)k * N * N + 1] = mk(T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x));
+  }
+  // deterministic tree reduction of |R| and the bad count
+  for (int s = G::kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x] += red[threadIdx.x + s];
+      redi[threadIdx.x] += redi[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const size_t g = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t groups = (size_t)gridDim.x * gridDim.y;
+    partial[((size_t)b * groups + g) * 2] = red[0];
+    partial[((size_t)b * groups + g) * 2 + 1] = double(redi[0]);
+  }
+}
+
+// Convergence control: one workgroup of 256 threads walks the batch.
+__global__ void __launch_bounds__(256)
+k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict__ ctl, SolveCfg cfg,
+           int* __restrict__ n_active) {
+  __shared__ double sr[256];
+  __shared__ double sb[256];
+  __shared__ int active;
+  if (threadIdx.x == 0) active = 0;
+  const double n3 = double(cfg.n) * cfg.n * cfg.n;
+  for (int b = 0; b < cfg.batch; ++b) {
+    __syncthreads();
+    if (ctl[b].done) continue;
+    double ar = 0.0, ab = 0.0;
+    for (int g = threadIdx.x; g < groups; g += 256) {
+      ar += partial[((size_t)b * groups + g) * 2];
+      ab += partial[((size_t)b * groups + g) * 2 + 1];
+    }
+    sr[threadIdx.x] = ar;
+    sb[threadIdx.x] = ab;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        sr[threadIdx.x] += sr[threadIdx.x + s];
+        sb[threadIdx.x] += sb[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      SolveCtl& C = ctl[b];
+      const double r = sr[0] / (n3 * C.eps);
+      const int nbad = int(sb[0]);
+      const int n = C.iters;
+      if (n < kMaxHist) C.hist[n] = r;
+      C.passes += 1;
+      bool done = false;
+      if (r <= cfg.tol) {
+        C.status = 0;
+        C.result = C.cur;
+        C.resid = r;
+        done = true;
+      } else if (r < C.resid_min) {
+        C.resid_min = r;
+        C.best = C.cur;
+      } else if (C.bad_seen) {
+        C.status = 2;
+        C.result = C.best;
+        C.resid = C.resid_min;
+        done = true;
+      }
+      if (r < C.resid_min) C.resid_min = r;
+      if (!done && n >= cfg.max_iter) {
+        C.status = 1;
+        C.result = C.best;
+        C.resid = C.resid_min;
+        done = true;
+      }
+      if (!done) {
+        C.last_bad = nbad;
+        C.bad_frac = double(nbad) / n3;
+        if (nbad > 0) C.bad_seen = 1;
+        C.iters = n + 1;
+        const int nc = C.out;
+        C.cur = nc;
+        C.out = 3 - nc - C.best;
+        ++active;
+      }
+      C.done = done ? 1 : 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *n_active = active;
+}
+
+// Per-batch mean of |x| and of x, deterministic two-level reduction.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_absmean_partial(const T* __restrict__ x, size_t n3, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  const T* xb = x + (size_t)b * n3;
+  double sa = 0.0, sm = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const double v = double(xb[i]);
+    sa += fabs(v);
+    sm += v;
+  }
+  __shared__ double ra[256], rm[256];
+  ra[threadIdx.x] = sa;
+  rm[threadIdx.x] = sm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      ra[threadIdx.x] += ra[threadIdx.x + s];
+      rm[threadIdx.x] += rm[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2] = ra[0];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = rm[0];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_absmean_final(const double* __restrict__ part, int groups, size_t n3, double* __restrict__ abs_mean,
+                double* __restrict__ mean) {
+  const int b = blockIdx.x;
+  __shared__ double ra[256], rm[256];
+  double sa = 0.0, sm = 0.0;
+  for (int g = threadIdx.x; g < groups; g += 256) {
+    sa += part[((size_t)b * groups + g) * 2];
+    sm += part[((size_t)b * groups + g) * 2 + 1];
+  }
+  ra[threadIdx.x] = sa;
+  rm[threadIdx.x] = sm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      ra[threadIdx.x] += ra[threadIdx.x + s];
+      rm[threadIdx.x] += rm[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (abs_mean) abs_mean[b] = ra[0] / double(n3);
+    if (mean) mean[b] = rm[0] / double(n3);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int N>
+static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
+                    const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
+  using G = AxisTile<T, N, 8>;
+  constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
+  dim3 grid(N / (2 * G::kTP), N, batch);
+  hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
+                     partial, mean_u, cfg, ctl, twiddles<T>(N));
+}
+
+template <typename T>
+void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
+                       const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
+  switch (n) {
+    case 8: relax_n<T, 8>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 16: relax_n<T, 16>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 32: relax_n<T, 32>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 64: relax_n<T, 64>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 128: relax_n<T, 128>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 256: relax_n<T, 256>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 512: relax_n<T, 512>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    default: break;
+  }
+}
+
+int relax_groups(int n, int elem_bytes) {
+  int tp = 0;
+#define C(NN)                                                                       \
+  case NN:                                                                          \
+    tp = (elem_bytes == 8) ? AxisTile<double, NN, 8>::kTP : AxisTile<float, NN, 8>::kTP; \
+    break;
+  switch (n) { C(8) C(16) C(32) C(64) C(128) C(256) C(512) default: return 0; }
+#undef C
+  return (n / (2 * tp)) * n;
+}
+
+void launch_finalize(const double* partial, int groups, SolveCtl* ctl, const SolveCfg& cfg, int* n_active,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, groups, ctl, cfg, n_active);
+}
+
+__global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  SolveCtl& C = ctl[b];
+  C.done = 0;
+  C.status = 0;
+  C.iters = 0;
+  C.cur = 0;
+  C.out = 1;
+  C.best = 2;
+  C.result = 0;
+  C.bad_seen = 0;
+  C.passes = 0;
+  C.last_bad = 0;
+  C.eps = eps[b];
+  C.resid = 0.0;
+  C.resid_min = __builtin_huge_val();
+  C.bad_frac = 0.0;
+  C.mean_u = 0.0;
+  for (int i = 0; i < kMaxHist; ++i) C.hist[i] = -1.0;
+}
+
+void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_init, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, eps, batch);
+}
+
+static int absmean_groups(size_t n3) {
+  size_t g = (n3 + 255) / 256;
+  return int(g > 1024 ? 1024 : g);
+}
+
+size_t absmean_scratch_doubles(size_t n3, int batch) { return (size_t)absmean_groups(n3) * batch * 2; }
+
+template <typename T>
+void launch_absmean(size_t n3, const T* x, int batch, double* scratch, double* abs_mean, double* mean,
+                    hipStream_t s) {
+  const int g = absmean_groups(n3);
+  hipLaunchKernelGGL((k_absmean_partial<T>), dim3(g, batch), dim3(256), 0, s, x, n3, scratch);
+  hipLaunchKernelGGL(k_absmean_final, dim3(batch), dim3(256), 0, s, scratch, g, n3, abs_mean, mean);
+}
+
+template void launch_relax<double>(int, const cx<double>*, double*, const double*, cx<double>*, double*,
+                                   const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t);
+template void launch_relax<float>(int, const cx<float>*, float*, const float*, cx<float>*, double*,
+                                  const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t);
+template void launch_absmean<double>(size_t, const double*, int, double*, double*, double*, hipStream_t);
+template void launch_absmean<float>(size_t, const float*, int, double*, double*, double*, hipStream_t);
+
+}  // namespace dgp

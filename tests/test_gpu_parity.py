@@ -1,0 +1,278 @@
+"""GPU (HIP, through the C-ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances: float64 path <= 1e-10 relative (element-wise comparisons in max norm
+where the oracle and the kernels perform the same operations); float32 path
+<= 1e-5 relative on the field, 1e-4 on P(k); integer deposit bit-exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import field as fld, pm, power, cosmology as cos  # noqa: E402
+from paper_0906_4548_amd import inputs  # noqa: E402
+from tests.gpu_common import OM0, to_dev, oracle_params, calibrate_lambda, gpu_params, rel_l2  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dgp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0906_4548_amd import dgp as mod
+    mod._lib.load()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ---------------------------------------------------------------- FFT
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fft_forward_inverse(dgp, n, prec):
+    say("fft", n, prec)
+    batch = 2
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((batch, n, n, n))
+    ref = np.fft.rfftn(x, axes=(2, 3, 1))        # real transform along axis 0 of each field
+    with dgp.Plan(n, 10.0, batch=batch, precision=prec) as plan:
+        xs = to_dev(x)
+        spec = torch.zeros((batch, n // 2 + 1, n, n), dtype=torch.complex128, device="cuda")
+        plan.fft_forward(xs, spec)
+        back = torch.zeros_like(xs)
+        plan.fft_inverse(spec, back)
+        torch.cuda.synchronize()
+        got = spec.cpu().numpy()
+        tol = 1e-13 if prec == 0 else 3e-6
+        assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref)) * np.sqrt(np.log2(n))
+        assert np.max(np.abs(back.cpu().numpy() - x)) <= (1e-13 if prec == 0 else 3e-6) * np.max(np.abs(x))
+
+
+# ---------------------------------------------------------------- field solve, float64
+def _c1(n=32, box=64.0, sigma=1.0, seed=1, rnl=3.0):
+    delta = inputs.lognormal_delta(n, box, sigma, seed)
+    lam = calibrate_lambda(delta, box, rnl)
+    return delta, lam
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3, 7])
+def test_solve_same_sequence_fp64(dgp, iters):
+    """Exactly `iters` updates from the linear guess: same arithmetic sequence as the oracle."""
+    say("solve same-seq", iters)
+    n, box = 32, 64.0
+    delta, lam = _c1(n, box)
+    op = oracle_params(lam=lam)
+    u_ref, info_ref = fld.solve(delta, box, op, fixed_iters=iters)
+    with dgp.Plan(n, box) as plan:
+        p = gpu_params(dgp, lam=lam, tol=0.0, max_iter=iters)
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(p, to_dev(delta), u)
+        torch.cuda.synchronize()
+        assert info[0]["iters"] == iters
+        assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-12 * np.max(np.abs(u_ref))
+        # residual history of the evaluated iterates
+        assert abs(info[0]["resid_min"] - min(info_ref.history)) <= 1e-10 * min(info_ref.history) + 1e-15
+
+
+def test_solve_converged_fp64_c1(dgp):
+    """32^3 log-normal (rms 1), screened (r_nl = 3), tolerance 1e-10 (config C1); plus C."""
+    say("solve C1")
+    n, box = 32, 64.0
+    delta, lam = _c1(n, box)
+    op = oracle_params(lam=lam, tol=1e-12, max_iter=100)
+    u_ref, info_ref = fld.solve(delta, box, op)
+    c_ref = fld.c_from_u(u_ref, box, op)
+    with dgp.Plan(n, box) as plan:
+        p = gpu_params(dgp, lam=lam, tol=1e-12, max_iter=100)
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        c = torch.zeros_like(u)
+        st, info = plan.solve_field(p, to_dev(delta), u, c)
+        torch.cuda.synchronize()
+        assert st == 0 and info[0]["resid"] <= 1e-12
+        assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-10
+        assert rel_l2(c.cpu().numpy(), c_ref) <= 1e-10
+        assert abs(info[0]["eps"] - info_ref.eps) <= 1e-13 * info_ref.eps
+        assert abs(info[0]["mean_u"] - info_ref.mean_u) <= 1e-12 * np.max(np.abs(u_ref))
+        # the paper's tolerance of 1e-10 on the same input
+        p2 = gpu_params(dgp, lam=lam, tol=1e-10, max_iter=100)
+        st2, info2 = plan.solve_field(p2, to_dev(delta), u)
+        _, i_ref2 = fld.solve(delta, box, op.with_(tol=1e-10))
+        assert st2 == 0 and info2[0]["iters"] == i_ref2.iters and info2[0]["resid"] <= 1e-10
+
+
+def test_solve_warm_zero_init_and_planar(dgp):
+    say("solve planar / init modes")
+    n, box = 16, 64.0
+    x = np.arange(n) * box / n
+    delta = 0.8 * np.cos(2 * np.pi * 3 * x / box)[None, :, None] * np.ones((n, n, n))
+    op = oracle_params(lam=1.0, tol=1e-13, init=fld.INIT_ZERO)
+    u_ref, iref = fld.solve(delta, box, op)
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=1.0, tol=1e-13, init=dgp.INIT_ZERO), to_dev(delta), u)
+        assert st == 0 and info[0]["iters"] == iref.iters
+        assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-12
+        # warm start from the answer: zero updates
+        st, info = plan.solve_field(gpu_params(dgp, lam=1.0, tol=1e-12, init=dgp.INIT_WARM), to_dev(delta), u)
+        assert st == 0 and info[0]["iters"] == 0
+
+
+def test_solve_bad_points_same_sequence(dgp):
+    """w = 0 at z = 4 on deep voids: bad points, stop at the minimum residual (same decisions)."""
+    say("solve bad points")
+    n, box = 16, 32.0
+    delta = inputs.lognormal_delta(n, box, 1.5, 21)
+    op = fld.SolveParams.from_cosmology(OM0, 0.2, tol=1e-12, max_iter=60, lam=1.0, w=0.0, init=fld.INIT_ZERO)
+    u_ref, iref = fld.solve(delta, box, op)
+    assert iref.status == fld.STATUS_BAD_POINTS
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        p = dgp.params(OM0, 0.2, lam=1.0, w=0.0, tol=1e-12, max_iter=60, init=dgp.INIT_ZERO)
+        st, info = plan.solve_field(p, to_dev(delta), u)
+        assert st == 2 and info[0]["status"] == 2
+        assert info[0]["iters"] == iref.iters
+        assert abs(info[0]["resid"] - iref.resid) <= 1e-9 * iref.resid
+        assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-9
+
+
+def test_solve_batched_fp64(dgp):
+    """Independent fields in one batched launch; each stops on its own (config C5 shape, smaller mesh)."""
+    say("solve batched")
+    n, box = 32, 64.0
+    sig = [0.3, 1.0, 3.0]
+    deltas = np.stack([inputs.lognormal_delta(n, box, s, 500 + i) for i, s in enumerate(sig)])
+    lams = [calibrate_lambda(d, box, 3.0) for d in deltas]
+    lam = float(np.median(lams))
+    with dgp.Plan(n, box, batch=len(sig)) as plan:
+        u = torch.zeros(deltas.shape, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=lam, tol=1e-11, max_iter=150), to_dev(deltas), u)
+        got = u.cpu().numpy()
+    for b in range(len(sig)):
+        u_ref, iref = fld.solve(deltas[b], box, oracle_params(lam=lam, tol=1e-11, max_iter=150))
+        assert info[b]["status"] == iref.status and info[b]["iters"] == iref.iters
+        assert rel_l2(got[b], u_ref) <= 1e-10
+
+
+# ---------------------------------------------------------------- PM
+@pytest.mark.parametrize("fp32", [False, True])
+def test_deposit_bit_exact(dgp, fp32):
+    say("deposit", fp32)
+    n, box = 32, 64.0
+    pos, _ = inputs.zeldovich_load(n, box, 11, dtype=np.float32 if fp32 else np.float64)
+    grid_ref, delta_ref = pm.deposit(pos, n, box)
+    with dgp.Plan(n, box) as plan:
+        tdt = torch.float32 if fp32 else torch.float64
+        g = torch.zeros(n ** 3, dtype=torch.int64, device="cuda")
+        d = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        plan.deposit(to_dev(pos, tdt), g, d)
+        assert np.array_equal(g.cpu().numpy().reshape(n, n, n), grid_ref)
+        assert np.max(np.abs(d.cpu().numpy().reshape(n, n, n) - delta_ref)) <= 1e-14
+        perm = np.random.default_rng(1).permutation(pos.shape[1])
+        g2 = torch.zeros_like(g)
+        plan.deposit(to_dev(pos[:, perm], tdt), g2, None)
+        assert torch.equal(g, g2)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_pm_forces(dgp, mode):
+    say("forces", mode)
+    n, box = 32, 64.0
+    pos, _ = inputs.zeldovich_load(n, box, 12)
+    _, delta = pm.deposit(pos, n, box)
+    lam = calibrate_lambda(delta, box, 3.0)
+    op = oracle_params(lam=lam, tol=1e-12)
+    u_ref, _ = fld.solve(delta, box, op)
+    f_ref, phik = pm.pm_forces(delta, u_ref, pos, box, op, OM0, 0.5, mode)
+    phi_ref = np.fft.irfftn(phik, s=(n, n, n), axes=(0, 1, 2))
+    with dgp.Plan(n, box) as plan:
+        p = gpu_params(dgp, lam=lam, force_mode=mode)
+        force = torch.zeros((3, pos.shape[1]), dtype=torch.float64, device="cuda")
+        phi = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        plan.pm_forces(p, to_dev(delta), to_dev(u_ref), to_dev(pos), force, phi)
+        assert rel_l2(force.cpu().numpy(), f_ref) <= 1e-10
+        assert rel_l2(phi.cpu().numpy().reshape(n, n, n), phi_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_step_matches_oracle(dgp, fp32):
+    say("step", fp32)
+    n, box, a, dlna = 32, 64.0, 0.5, 0.005
+    dt = np.float32 if fp32 else np.float64
+    pos, psi = inputs.zeldovich_load(n, box, 13, dtype=dt)
+    c = cos.coefficients(OM0, a)
+    vel = (a * a * c.E * cos.omega_m_of_a(OM0, a) ** 0.55 * psi).astype(dt)
+    _, delta = pm.deposit(pos, n, box)
+    # r_nl = 1.78 (screened, solvable for this particle load; r_nl >= 3 leaves bad points in its voids)
+    lam = calibrate_lambda(delta, box, 1.78)
+    op = oracle_params(lam=lam, tol=1e-11)
+    x_ref, v_ref, u_ref, info_ref = pm.step(pos, vel, None, a, dlna, box, n, op, OM0)
+    with dgp.Plan(n, box) as plan:
+        tdt = torch.float32 if fp32 else torch.float64
+        tp, tv = to_dev(pos, tdt), to_dev(vel, tdt)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.step(gpu_params(dgp, lam=lam, tol=1e-11), tp, tv, u, dlna)
+        assert st == 0 and info["iters"] == info_ref.iters
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= 1e-10
+        # displacement of the step (positions themselves carry the lattice offset)
+        dx = (tp.cpu().numpy().astype(np.float64) - pos.astype(np.float64) + box / 2) % box - box / 2
+        dx_ref = (x_ref.astype(np.float64) - pos.astype(np.float64) + box / 2) % box - box / 2
+        tol_x = 1e-10 if not fp32 else 2e-5
+        assert rel_l2(dx, dx_ref) <= tol_x
+        assert rel_l2(tv.cpu().numpy(), v_ref) <= (1e-12 if not fp32 else 1e-7)
+
+
+def test_step_bad_point_regime_same_decisions(dgp):
+    """r_nl = 10 on a particle load: the relaxation meets bad points in voids and stops at its
+    minimum residual (Sec. III C); GPU and oracle take the same decisions (parity of this regime is
+    same-sequence agreement only)."""
+    say("step r_nl 10")
+    n, box = 32, 64.0
+    pos, _ = inputs.zeldovich_load(n, box, 13)
+    _, delta = pm.deposit(pos, n, box)
+    lam = calibrate_lambda(delta, box, 10.0)
+    u_ref, iref = fld.solve(delta, box, oracle_params(lam=lam, tol=1e-11, max_iter=100))
+    assert iref.status == fld.STATUS_BAD_POINTS
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=lam, tol=1e-11, max_iter=100), to_dev(delta), u)
+        assert st == 2 and info[0]["iters"] == iref.iters
+        assert abs(info[0]["resid"] - iref.resid) <= 1e-8 * iref.resid
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= 1e-8
+
+
+def test_power_spectrum(dgp):
+    say("power")
+    n, box = 32, 64.0
+    delta = inputs.lognormal_delta(n, box, 1.0, 3)
+    pk_ref, cnt_ref, _ = power.power_spectrum(delta, box)
+    op = oracle_params()
+    u = fld.linear_solution(fld.source(delta, box, op)[1], box, op)
+    pkc_ref, _, _ = power.power_spectrum(fld.c_from_u(u, box, op), box)
+    with dgp.Plan(n, box) as plan:
+        p = gpu_params(dgp)
+        pk, cnt = plan.power_spectrum(p, to_dev(delta))
+        assert np.array_equal(cnt, cnt_ref)
+        assert np.max(np.abs(pk[0] - pk_ref) / np.where(pk_ref > 0, pk_ref, 1)) <= 1e-12
+        pkc, _ = plan.power_spectrum(p, to_dev(u), of_c=True)
+        assert np.max(np.abs(pkc[0] - pkc_ref) / np.where(pkc_ref > 0, pkc_ref, 1)) <= 1e-12
+
+
+# ---------------------------------------------------------------- errors
+def test_invalid_arguments(dgp):
+    say("errors")
+    with pytest.raises(dgp._lib.DGPError):
+        dgp.Plan(24, 10.0)
+    with pytest.raises(dgp._lib.DGPError):
+        dgp.Plan(32, -1.0)
+    with dgp.Plan(16, 32.0) as plan:
+        d = torch.zeros(16 ** 3, dtype=torch.float64, device="cuda")
+        u = torch.zeros_like(d)
+        for bad in (dict(lam=float("nan")), dict(w=1.0), dict(lam=-1.0), dict(max_iter=-1)):
+            with pytest.raises(dgp._lib.DGPError) as e:
+                plan.solve_field(gpu_params(dgp, **bad), d, u)
+            assert e.value.code == -1
