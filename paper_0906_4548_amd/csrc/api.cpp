@@ -208,7 +208,8 @@ struct dgp_plan {
   double* bin_partial = nullptr;
   double* bin_host = nullptr;        // pinned
   // adjoint (allocated on first use)
-  double* adj = nullptr;             // [13][B][n3]
+  double* adj = nullptr;             // [15][B][n3]
+  double* adj_red = nullptr;
   std::vector<void*> dev_allocs;
   std::vector<void*> host_allocs;
   size_t bytes = 0;
@@ -953,10 +954,90 @@ extern "C" int dgp_solve_field_backward(dgp_plan* pl, const dgp_params* p, const
   return adjoint_solve(pl, p, delta, u_star, grad_u, grad_delta, info, static_cast<hipStream_t>(stream));
 }
 
+// Transposed relaxation mu <- D^{-1} (g + M^T mu) (see adjoint.hip), then dL/ddelta = S mu.
 int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star, const double* grad_u,
                   double* grad_delta, dgp_info* info, hipStream_t s) {
-  (void)pl; (void)p; (void)delta; (void)u_star; (void)grad_u; (void)grad_delta; (void)info; (void)s;
-  return fail(DGP_E_UNSUPPORTED, "adjoint not built yet");
+  (void)delta;   // S does not depend on delta; the solve's delta only fixed u*
+  const int n = pl->n, B = pl->batch;
+  const size_t n3 = pl->n3, fs = (size_t)B * pl->hs, bn = (size_t)B * n3;
+  if (!pl->adj) {
+    TRY(dalloc(pl, &pl->adj, 15 * bn));
+    TRY(dalloc(pl, &pl->adj_red, (size_t)adjoint_groups(n3) * B * 2));
+  }
+  double* H5 = pl->adj;
+  double* P6 = pl->adj + 5 * bn;
+  double* MU = pl->adj + 11 * bn;
+  double* MU2 = pl->adj + 12 * bn;
+  double* Q = pl->adj + 13 * bn;
+  double* RES = pl->adj + 14 * bn;
+  const SpecCoef cf = spec_coef(pl, p);
+  const double lam = p->lambda, w = p->w, alpha = p->alpha;
+  const int G = adjoint_groups(n3);
+  // Hessians of u* (h00, h11, h01, h02, h12) and <u*>
+  TRY(fwd3<double>(pl, u_star, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_FANOUT6, pl->spec_u, fs, 1, pl->spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, nullptr,
+                    s);
+  launch_p2<double>(n, pl->spec6, 6, B, +1, nullptr, s);
+  for (int f = 0; f < 5; ++f) launch_p1_inv<double>(n, pl->spec6 + f * fs, H5 + f * bn, B, nullptr, s);
+  launch_adj_init(n3, B, grad_u, u_star, MU, 2.0 * (1.0 - w) * lam, alpha, s);
+  LAUNCHCHK();
+  std::vector<int> done(B, 0), iters(B, 0);
+  std::vector<double> resid(B, 0.0), rmin(B, 1e300), host(2 * B);
+  int it = 0;
+  for (;; ++it) {
+    launch_adj_products(n3, B, MU, u_star, H5, pl->mean_u, P6, pl->adj_red, s);
+    launch_pair_means(pl->adj_red, G, n3, B, pl->vec, nullptr, s);
+    launch_p1_fwd<double>(n, P6, pl->spec6, 6 * B, nullptr, s);
+    launch_p2<double>(n, pl->spec6, 6, B, -1, nullptr, s);
+    launch_p3<double>(n, SPEC_ADJ_COMBINE, pl->spec6, fs, 6, pl->spec_u, fs, 1, B, cf, nullptr, nullptr, nullptr,
+                      nullptr, s);
+    launch_p2<double>(n, pl->spec_u, 1, B, +1, nullptr, s);
+    launch_p1_inv<double>(n, pl->spec_u, Q, B, nullptr, s);
+    launch_adj_update(n3, B, Q, MU, MU2, u_star, H5, pl->mean_u, pl->vec, grad_u, lam, w, alpha, pl->adj_red, s);
+    launch_pair_means(pl->adj_red, G, n3, B, pl->vec + B, pl->vec + 2 * B, s);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(host.data(), pl->vec + B, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int active = 0;
+    for (int b = 0; b < B; ++b) {
+      if (done[b]) continue;
+      const double r = host[B + b] > 0.0 ? host[b] / host[B + b] : 0.0;
+      resid[b] = r;
+      rmin[b] = std::min(rmin[b], r);
+      if (r <= p->tol || it >= p->max_iter) {
+        done[b] = (r <= p->tol) ? 1 : 2;
+        iters[b] = it;
+        HIPCHK(hipMemcpyAsync(RES + (size_t)b * n3, MU + (size_t)b * n3, sizeof(double) * n3,
+                              hipMemcpyDeviceToDevice, s));
+      } else {
+        ++active;
+      }
+    }
+    if (active == 0) break;
+    std::swap(MU, MU2);
+  }
+  // dL/ddelta = S mu (multiplier A (1 - beta/kbar), k = 0 -> 0)
+  TRY(fwd3<double>(pl, RES, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_SOURCE, pl->spec_u, fs, 1, pl->spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
+  launch_p2<double>(n, pl->spec6, 1, B, +1, nullptr, s);
+  launch_p1_inv<double>(n, pl->spec6, grad_delta, B, nullptr, s);
+  LAUNCHCHK();
+  HIPCHK(hipStreamSynchronize(s));
+  int worst = DGP_OK;
+  for (int b = 0; b < B; ++b) {
+    const int st = done[b] == 1 ? DGP_OK : DGP_NOT_CONVERGED;
+    if (st != DGP_OK) worst = st;
+    if (info) {
+      std::memset(&info[b], 0, sizeof(dgp_info));
+      info[b].status = st;
+      info[b].iters = iters[b];
+      info[b].passes = iters[b] + 1;
+      info[b].passes_fp64 = iters[b] + 1;
+      info[b].resid = resid[b];
+      info[b].resid_min = rmin[b];
+    }
+  }
+  return worst;
 }
 
 // ------------------------------------------------------------------ live kernel timing

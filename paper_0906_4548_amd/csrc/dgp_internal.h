@@ -136,6 +136,20 @@ size_t absmean_scratch_doubles(size_t n3, int batch);
 // control blocks: eps from abs_mean[b], buffer roles reset
 void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s);
 
+// per-batch means of the two columns of [batch][groups][2] partial sums
+void launch_pair_means(const double* part, int groups, size_t n3, int batch, double* out0, double* out1,
+                       hipStream_t s);
+
+// adjoint (transposed relaxation) pointwise kernels
+int adjoint_groups(size_t n3);
+void launch_adj_init(size_t n3, int batch, const double* g, const double* u, double* mu, double dscale, double alpha,
+                     hipStream_t s);
+void launch_adj_products(size_t n3, int batch, const double* mu, const double* u, const double* h5,
+                         const double* mean_u, double* p6, double* part, hipStream_t s);
+void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, double* mu_new, const double* u,
+                       const double* h5, const double* mean_u, const double* mean_h22mu, const double* g, double lam,
+                       double w, double alpha, double* part, hipStream_t s);
+
 // PM kernels
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
                     hipStream_t s);

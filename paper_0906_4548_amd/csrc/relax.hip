@@ -370,6 +370,11 @@ void launch_absmean(size_t n3, const T* x, int batch, double* scratch, double* a
   hipLaunchKernelGGL(k_absmean_final, dim3(batch), dim3(256), 0, s, scratch, g, n3, abs_mean, mean);
 }
 
+void launch_pair_means(const double* part, int groups, size_t n3, int batch, double* out0, double* out1,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_absmean_final, dim3(batch), dim3(256), 0, s, part, groups, n3, out0, out1);
+}
+
 template void launch_relax<double>(int, const cx<double>*, double*, const double*, cx<double>*, double*,
                                    const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t);
 template void launch_relax<float>(int, const cx<float>*, float*, const float*, cx<float>*, double*,
