@@ -3,7 +3,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdgp.so")
+LIB_PATH = os.environ.get("DGP_LIB_PATH") or os.path.join(HERE, "libdgp.so")
 
 DGP_OK, DGP_NOT_CONVERGED, DGP_BAD_POINTS = 0, 1, 2
 DGP_E_INVALID, DGP_E_NOMEM, DGP_E_HIP, DGP_E_UNSUPPORTED = -1, -2, -3, -4

@@ -160,23 +160,38 @@ __device__ __forceinline__ void dft_small(cx<T>* v) {
 
 // Radix plans: R elements per thread, stage radices (first == R, others divide R).
 template <int N> struct Plan;
-template <> struct Plan<8>   { static constexpr int R = 8;  static constexpr int S = 1; static constexpr int r[3] = {8, 0, 0}; };
-template <> struct Plan<16>  { static constexpr int R = 16; static constexpr int S = 1; static constexpr int r[3] = {16, 0, 0}; };
-template <> struct Plan<32>  { static constexpr int R = 8;  static constexpr int S = 2; static constexpr int r[3] = {8, 4, 0}; };
-template <> struct Plan<64>  { static constexpr int R = 8;  static constexpr int S = 2; static constexpr int r[3] = {8, 8, 0}; };
-template <> struct Plan<128> { static constexpr int R = 16; static constexpr int S = 2; static constexpr int r[3] = {16, 8, 0}; };
-template <> struct Plan<256> { static constexpr int R = 16; static constexpr int S = 2; static constexpr int r[3] = {16, 16, 0}; };
-template <> struct Plan<512> { static constexpr int R = 8;  static constexpr int S = 3; static constexpr int r[3] = {8, 8, 8}; };
+template <> struct Plan<8>   { static constexpr int R = 8;  static constexpr int S = 1; static constexpr int r[5] = {8, 0, 0, 0, 0}; };
+template <> struct Plan<16>  { static constexpr int R = 16; static constexpr int S = 1; static constexpr int r[5] = {16, 0, 0, 0, 0}; };
+template <> struct Plan<32>  { static constexpr int R = 8;  static constexpr int S = 2; static constexpr int r[5] = {8, 4, 0, 0, 0}; };
+template <> struct Plan<64>  { static constexpr int R = 8;  static constexpr int S = 2; static constexpr int r[5] = {8, 8, 0, 0, 0}; };
+template <> struct Plan<128> { static constexpr int R = 16; static constexpr int S = 2; static constexpr int r[5] = {16, 8, 0, 0, 0}; };
+template <> struct Plan<256> { static constexpr int R = 16; static constexpr int S = 2; static constexpr int r[5] = {16, 16, 0, 0, 0}; };
+template <> struct Plan<512> { static constexpr int R = 8;  static constexpr int S = 3; static constexpr int r[5] = {8, 8, 8, 0, 0}; };
 
 // Plans with at most 8 elements per thread (for kernels that keep extra per-element state).
 template <int N> struct Plan8;
-template <> struct Plan8<8>   { static constexpr int R = 8; static constexpr int S = 1; static constexpr int r[3] = {8, 0, 0}; };
-template <> struct Plan8<16>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[3] = {8, 2, 0}; };
-template <> struct Plan8<32>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[3] = {8, 4, 0}; };
-template <> struct Plan8<64>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[3] = {8, 8, 0}; };
-template <> struct Plan8<128> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[3] = {8, 8, 2}; };
-template <> struct Plan8<256> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[3] = {8, 8, 4}; };
-template <> struct Plan8<512> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[3] = {8, 8, 8}; };
+template <> struct Plan8<8>   { static constexpr int R = 8; static constexpr int S = 1; static constexpr int r[5] = {8, 0, 0, 0, 0}; };
+template <> struct Plan8<16>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[5] = {8, 2, 0, 0, 0}; };
+template <> struct Plan8<32>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[5] = {8, 4, 0, 0, 0}; };
+template <> struct Plan8<64>  { static constexpr int R = 8; static constexpr int S = 2; static constexpr int r[5] = {8, 8, 0, 0, 0}; };
+template <> struct Plan8<128> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[5] = {8, 8, 2, 0, 0}; };
+template <> struct Plan8<256> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[5] = {8, 8, 4, 0, 0}; };
+template <> struct Plan8<512> { static constexpr int R = 8; static constexpr int S = 3; static constexpr int r[5] = {8, 8, 8, 0, 0}; };
+
+// Plans with 4 elements per thread (twice the threads per transform, more LDS exchanges).
+template <int N> struct Plan4;
+template <> struct Plan4<8>   { static constexpr int R = 4; static constexpr int S = 2; static constexpr int r[5] = {4, 2, 0, 0, 0}; };
+template <> struct Plan4<16>  { static constexpr int R = 4; static constexpr int S = 2; static constexpr int r[5] = {4, 4, 0, 0, 0}; };
+template <> struct Plan4<32>  { static constexpr int R = 4; static constexpr int S = 3; static constexpr int r[5] = {4, 4, 2, 0, 0}; };
+template <> struct Plan4<64>  { static constexpr int R = 4; static constexpr int S = 3; static constexpr int r[5] = {4, 4, 4, 0, 0}; };
+template <> struct Plan4<128> { static constexpr int R = 4; static constexpr int S = 4; static constexpr int r[5] = {4, 4, 4, 2, 0}; };
+template <> struct Plan4<256> { static constexpr int R = 4; static constexpr int S = 4; static constexpr int r[5] = {4, 4, 4, 4, 0}; };
+template <> struct Plan4<512> { static constexpr int R = 4; static constexpr int S = 5; static constexpr int r[5] = {4, 4, 4, 4, 2}; };
+
+// Plan selection: 0 = at most 8 elements per thread (Plan8), 1 = up to 16 (Plan).
+template <int N, int SEL> struct PlanPick { using type = Plan8<N>; };
+template <int N> struct PlanPick<N, 1> { using type = Plan<N>; };
+template <int N> struct PlanPick<N, 2> { using type = Plan4<N>; };
 
 // One Stockham stage.  v: the thread's R registers.  lds: accessor with
 // load(e), store(e, value) for element e of this thread's transform.  The
@@ -230,20 +245,19 @@ __device__ __forceinline__ void fft_stage(cx<T> (&v)[R], const cx<T>* __restrict
   }
 }
 
-// Full N-point transform with plan P (P::R must equal R).
+// Stages I..S-1 of plan P; NS is the span before stage I.
+template <typename T, int N, class P, int DIR, int I, int NS, class Lds>
+__device__ __forceinline__ void fft_stages(cx<T> (&v)[P::R], const cx<T>* __restrict__ tw, Lds& lds, int t) {
+  if constexpr (I < P::S) {
+    fft_stage<T, N, P::R, P::r[I], NS, I == 0, I == P::S - 1, DIR>(v, tw, lds, t);
+    fft_stages<T, N, P, DIR, I + 1, NS * P::r[I]>(v, tw, lds, t);
+  }
+}
+
+// Full N-point transform with plan P.
 template <typename T, int N, class P, int DIR, class Lds>
 __device__ __forceinline__ void fft(cx<T> (&v)[P::R], const cx<T>* __restrict__ tw, Lds& lds, int t) {
-  constexpr int R = P::R;
-  if constexpr (P::S == 1) {
-    fft_stage<T, N, R, P::r[0], 1, true, true, DIR>(v, tw, lds, t);
-  } else if constexpr (P::S == 2) {
-    fft_stage<T, N, R, P::r[0], 1, true, false, DIR>(v, tw, lds, t);
-    fft_stage<T, N, R, P::r[1], P::r[0], false, true, DIR>(v, tw, lds, t);
-  } else {
-    fft_stage<T, N, R, P::r[0], 1, true, false, DIR>(v, tw, lds, t);
-    fft_stage<T, N, R, P::r[1], P::r[0], false, false, DIR>(v, tw, lds, t);
-    fft_stage<T, N, R, P::r[2], P::r[0] * P::r[1], false, true, DIR>(v, tw, lds, t);
-  }
+  fft_stages<T, N, P, DIR, 0, 1>(v, tw, lds, t);
 }
 
 // LDS accessor for strided columns: element e of column c at base[e * C + c].

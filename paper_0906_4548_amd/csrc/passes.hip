@@ -22,13 +22,33 @@
 namespace dgp {
 
 // radix plan and workgroup shapes of each pass, per element type and mesh size
+// Plan choice per pass and element type (0: 8 elements per thread, 1: up to 16,
+// 2: 4), picked from measured pass times at 256^3 on gfx950.
+#ifndef DGP_PLAN_P1
+#define DGP_PLAN_P1 0
+#endif
+#ifndef DGP_PLAN_P2_F64
+#define DGP_PLAN_P2_F64 1
+#endif
+#ifndef DGP_PLAN_P2_F32
+#define DGP_PLAN_P2_F32 1
+#endif
+#ifndef DGP_PLAN_P3_F64
+#define DGP_PLAN_P3_F64 0
+#endif
+#ifndef DGP_PLAN_P3_F32
+#define DGP_PLAN_P3_F32 2
+#endif
 template <typename T, int N>
 struct Geo {
-  using P = Plan8<N>;
+  static constexpr bool kF32 = sizeof(T) == 4;
+  using P = typename PlanPick<N, DGP_PLAN_P1>::type;
+  using P2 = typename PlanPick<N, kF32 ? DGP_PLAN_P2_F32 : DGP_PLAN_P2_F64>::type;
+  using P3 = typename PlanPick<N, kF32 ? DGP_PLAN_P3_F32 : DGP_PLAN_P3_F64>::type;
   static constexpr int R = P::R;
   static constexpr int kP1 = AxisTile<T, N, R>::kThreads;
-  static constexpr int kP2 = ColTile<T, N, R>::kThreads;
-  static constexpr int kP3 = RowTile<N, R>::kThreads;
+  static constexpr int kP2 = ColTile<T, N, P2::R>::kThreads;
+  static constexpr int kP3 = RowTile<N, P3::R>::kThreads;
 };
 
 __device__ __forceinline__ bool batch_done(const SolveCtl* ctl, int b) {
@@ -120,7 +140,7 @@ k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restr
 template <typename T, int N, int DIR>
 __global__ void __launch_bounds__((Geo<T, N>::kP2))
 k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const SolveCtl* __restrict__ ctl) {
-  using P = typename Geo<T, N>::P;
+  using P = typename Geo<T, N>::P2;
   constexpr int R = P::R;
   using G = ColTile<T, N, R>;
   constexpr int TY = G::kTY, TT = G::kT, H = N / 2 + 1;
@@ -163,7 +183,7 @@ __global__ void __launch_bounds__((Geo<T, N>::kP3))
 k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, size_t out_stride,
      const cx<T>* __restrict__ tw, SpecCoef cf, const double* __restrict__ bin_coef,
      double* __restrict__ bin_partial, double* __restrict__ mean_out, const SolveCtl* __restrict__ ctl) {
-  using P = typename Geo<T, N>::P;
+  using P = typename Geo<T, N>::P3;
   constexpr int R = P::R;
   using G = RowTile<N, R>;
   constexpr int RW = G::kRW, TT = G::kT, H = N / 2 + 1;
@@ -204,14 +224,19 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
     store_row(out, v);
     return;
   } else if constexpr (MODE == SPEC_POWER) {
-    __shared__ double bins[2 * 128];
-    for (int i = threadIdx.x; i < 2 * cf.nbins; i += blockDim.x) bins[i] = 0.0;
+    // deterministic binning: every mode's (bin, weighted |f|^2) goes to LDS, then thread b sums
+    // bin b over the workgroup's modes in a fixed order
+    constexpr int NE = G::kThreads * R;
+    __shared__ double pval[NE];
+    __shared__ short pbin[NE];
     load_row(in);
     fft<T, N, P, -1>(v, tw, L, t);
-    __syncthreads();
-    if (valid) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
+    for (int q = 0; q < R; ++q) {
+      const int slot = (c * R + q) * TT + t;
+      short bin = -1;
+      double val = 0.0;
+      if (valid) {
         const Mode3 m = mode_of(N, k0, k1, t + q * TT);
         const double ms = double(m.msq);
         if (ms >= bin_coef[0] && ms < bin_coef[cf.nbins]) {
@@ -226,14 +251,27 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
             const double kb2 = cf.kappa * cf.kappa * kf * kf * ms;
             p2 /= kb2 * kb2;
           }
-          atomicAdd(&bins[lo], mult * p2);
-          atomicAdd(&bins[cf.nbins + lo], mult);
+          bin = short(lo);
+          val = mult * p2;
         }
       }
+      pval[slot] = val;
+      pbin[slot] = bin;
     }
     __syncthreads();
     double* dstp = bin_partial + ((size_t)b * gridDim.x + blockIdx.x) * 2 * cf.nbins;
-    for (int i = threadIdx.x; i < 2 * cf.nbins; i += blockDim.x) dstp[i] = bins[i];
+    for (int bb = threadIdx.x; bb < cf.nbins; bb += blockDim.x) {
+      double sum = 0.0, cnt = 0.0;
+      for (int i = 0; i < NE; ++i) {
+        if (pbin[i] == bb) {
+          sum += pval[i];
+          const int kk0 = (blockIdx.x * RW + i / (TT * R)) / N;   // plane of the mode's row
+          cnt += (kk0 == 0 || kk0 == N / 2) ? 1.0 : 2.0;
+        }
+      }
+      dstp[bb] = sum;
+      dstp[cf.nbins + bb] = cnt;
+    }
     return;
   } else if constexpr (MODE == SPEC_ADJ_COMBINE) {
     cx<T> acc[R];
@@ -382,7 +420,7 @@ static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, co
 }
 template <typename T, int N>
 static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
-  using G = ColTile<T, N, Geo<T, N>::R>;
+  using G = ColTile<T, N, Geo<T, N>::P2::R>;
   dim3 grid(N / G::kTY, N / 2 + 1, nf * batch);
   if (dir < 0) hipLaunchKernelGGL((k_p2<T, N, -1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);
   else hipLaunchKernelGGL((k_p2<T, N, +1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);
@@ -390,7 +428,7 @@ static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, c
 template <typename T, int N>
 static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t os, int batch, const SpecCoef& cf,
                  const double* bc, double* bp, double* mean, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
-  using G = RowTile<N, Geo<T, N>::R>;
+  using G = RowTile<N, Geo<T, N>::P3::R>;
   constexpr int ROWS = (N / 2 + 1) * N;
   dim3 grid((ROWS + G::kRW - 1) / G::kRW, batch);
   dim3 blk(G::kThreads);
@@ -458,11 +496,11 @@ void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin,
 #undef C
 }
 
-int p3_row_groups(int n) {
+int p3_row_groups(int n) {   // row groups of the float64 axis-2 pass (the P(k) binning uses it)
   int r = 0;
 #define C(NN)                                                          \
   {                                                                    \
-    using G = RowTile<NN, Plan8<NN>::R>;                               \
+    using G = RowTile<NN, Geo<double, NN>::P3::R>;                     \
     r = ((NN / 2 + 1) * NN + G::kRW - 1) / G::kRW;                     \
   }
   DGP_DISPATCH_N(n, C)

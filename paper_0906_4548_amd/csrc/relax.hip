@@ -18,6 +18,8 @@
 // A single-workgroup kernel then forms r = <|R|>/eps (Eq. normres) per batch
 // element and runs the stopping rules; kernels of later passes read the
 // per-element `done` flag and exit at once.
+#include <type_traits>
+
 #include "dgp_internal.h"
 
 namespace dgp {
@@ -25,17 +27,46 @@ namespace dgp {
 template <typename T>
 const cx<T>* twiddles(int n);
 
+#ifndef DGP_PLAN_RELAX
+#define DGP_PLAN_RELAX 2
+#endif
+#ifndef DGP_RELAX_F32ACC
+#define DGP_RELAX_F32ACC 1
+#endif
+#ifndef DGP_RELAX_PREFETCH
+#define DGP_RELAX_PREFETCH 1
+#endif
+#ifndef DGP_RELAX_PRELOAD
+#define DGP_RELAX_PRELOAD 0
+#endif
+
 template <typename T, int N>
-__global__ void __launch_bounds__((AxisTile<T, N, 8>::kThreads))
+struct RelaxGeo {
+  using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
+  static constexpr int R = P::R;
+  using G = AxisTile<T, N, R>;
+  // accumulators of the float32 form may be float32 (pointwise arithmetic in the
+  // precision of the fields); the residual, discriminant and root stay float64
+  using Acc = typename std::conditional<(sizeof(T) == 4 && DGP_RELAX_F32ACC), float, double>::type;
+};
+
+template <typename T, int N>
+__global__ void __launch_bounds__((RelaxGeo<T, N>::G::kThreads))
 k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
         cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
         const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
-  using P = Plan8<N>;
+  using RG = RelaxGeo<T, N>;
+  using P = typename RG::P;
+  using Acc = typename RG::Acc;
   constexpr int R = P::R;
-  using G = AxisTile<T, N, R>;
+  using G = typename RG::G;
   constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
   constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
+  constexpr int NPF = (H + TT - 1) / TT;   // tile rows loaded per thread
   constexpr size_t N3 = (size_t)N * N * N;
+  // the next field's tile is fetched into registers during the current transform
+  // (float only: for double the staging registers make the compiler spill)
+  constexpr bool kPrefetch = DGP_RELAX_PREFETCH && sizeof(T) == 4;
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
@@ -47,17 +78,57 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   __shared__ int redi[G::kThreads];
   LdsCol<T, TP> L{lds, c};
 
-  cx<double> s2[R], h22[R];
+  // software pipeline: the tile of field f+1 is fetched into registers while field f is transformed
+  const size_t col = (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  cx<T> pf[NPF][2];
+  auto fetch = [&](int f) {
+    const cx<T>* src = spec6 + f * fstride + col;
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+      const int k = t + r * TT;
+      if (k < H) {
+        pf[r][0] = src[(size_t)k * N * N];
+        pf[r][1] = src[(size_t)k * N * N + 1];
+      }
+    }
+  };
+  if (kPrefetch) fetch(0);
+
+  Acc s2[R][2], h22[R][2];
   cx<T> v[R];
+  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
+  cx<T> up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    const cx<T>* src = spec6 + f * fstride + (size_t)b * H * N * N + (size_t)i1 * N + i2;
     __syncthreads();
-    for (int k = t; k < H; k += TT) {
-      lds[k * 2 * TP + 2 * c] = src[(size_t)k * N * N];
-      lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
+    if constexpr (kPrefetch) {
+#pragma unroll
+      for (int r = 0; r < NPF; ++r) {
+        const int k = t + r * TT;
+        if (k < H) {
+          lds[k * 2 * TP + 2 * c] = pf[r][0];
+          lds[k * 2 * TP + 2 * c + 1] = pf[r][1];
+        }
+      }
+    } else {
+      const cx<T>* src = spec6 + f * fstride + col;
+      for (int k = t; k < H; k += TT) {
+        lds[k * 2 * TP + 2 * c] = src[(size_t)k * N * N];
+        lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
+      }
     }
     __syncthreads();
+    if (f < 5) {
+      if (kPrefetch) fetch(f + 1);
+    } else if (DGP_RELAX_PRELOAD) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const size_t off = (size_t)(t + q * TT) * N * N;
+        up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
+        spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int e = t + q * TT;
@@ -73,17 +144,24 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       v[q] = mk(xa.x - xb.y, xa.y + xb.x);
     }
     fft<T, N, P, +1>(v, tw, L, t);
+    if (f < 5) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const double hx = double(v[q].x), hy = double(v[q].y);
-      if (f == 0) {
-        s2[q] = mk(hx * hx, hy * hy);
-        h22[q] = mk(-hx, -hy);
-      } else if (f == 1) {
-        s2[q] = mk(s2[q].x + hx * hx, s2[q].y + hy * hy);
-        h22[q] = mk(h22[q].x - hx, h22[q].y - hy);
-      } else if (f < 5) {
-        s2[q] = mk(s2[q].x + 2.0 * hx * hx, s2[q].y + 2.0 * hy * hy);
+      for (int q = 0; q < R; ++q) {
+        const Acc hx = Acc(v[q].x), hy = Acc(v[q].y);
+        if (f == 0) {
+          s2[q][0] = hx * hx;
+          s2[q][1] = hy * hy;
+          h22[q][0] = -hx;
+          h22[q][1] = -hy;
+        } else if (f == 1) {
+          s2[q][0] += hx * hx;
+          s2[q][1] += hy * hy;
+          h22[q][0] -= hx;
+          h22[q][1] -= hy;
+        } else {
+          s2[q][0] += Acc(2) * hx * hx;
+          s2[q][1] += Acc(2) * hy * hy;
+        }
       }
     }
   }
@@ -92,24 +170,24 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   const double mu = mean_u[b];
   const double vertex = -alpha / (2.0 * (1.0 - w) * lam);
   const double c4 = 4.0 * (1.0 - w) * lam;
-  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
   T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
-  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
   double abs_r = 0.0;
   int nbad = 0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const size_t off = (size_t)(t + q * TT) * N * N;
-    const cx<T> up = *reinterpret_cast<const cx<T>*>(uin + off);
-    const cx<T> spv = *reinterpret_cast<const cx<T>*>(sp + off);
+    if (!DGP_RELAX_PRELOAD) {
+      up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
+      spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
+    }
     double un[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const double u = double(j ? up.y : up.x);
-      const double s = double(j ? spv.y : spv.x);
+      const double u = double(j ? up[q].y : up[q].x);
+      const double s = double(j ? spv[q].y : spv[q].x);
       const double nf = double(j ? v[q].y : v[q].x);
-      const double hz = (j ? h22[q].y : h22[q].x) + (u - mu);
-      const double sh2 = (j ? s2[q].y : s2[q].x) + hz * hz;
+      const double hz = double(h22[q][j]) + (u - mu);
+      const double sh2 = double(s2[q][j]) + hz * hz;
       const double res = lam * (u * u - sh2) + alpha * u + gamma * nf - s;
       abs_r += fabs(res);
       const double bp = lam * (sh2 - w * u * u) - gamma * nf + s;
@@ -136,7 +214,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   red[threadIdx.x] = abs_r;
   redi[threadIdx.x] = nbad;
   __syncthreads();
-  cx<T>* dst = spec_u + (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  cx<T>* dst = spec_u + col;
   for (int k = t; k < H; k += TT) {
     const cx<T> zk = lds[k * TP + c];
     const cx<T> zn = lds[((N - k) & (N - 1)) * TP + c];
@@ -291,7 +369,7 @@ k_absmean_final(const double* __restrict__ part, int groups, size_t n3, double* 
 template <typename T, int N>
 static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
                     const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
-  using G = AxisTile<T, N, 8>;
+  using G = typename RelaxGeo<T, N>::G;
   constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
   dim3 grid(N / (2 * G::kTP), N, batch);
   hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
@@ -317,7 +395,7 @@ int relax_groups(int n, int elem_bytes) {
   int tp = 0;
 #define C(NN)                                                                       \
   case NN:                                                                          \
-    tp = (elem_bytes == 8) ? AxisTile<double, NN, 8>::kTP : AxisTile<float, NN, 8>::kTP; \
+    tp = (elem_bytes == 8) ? RelaxGeo<double, NN>::G::kTP : RelaxGeo<float, NN>::G::kTP; \
     break;
   switch (n) { C(8) C(16) C(32) C(64) C(128) C(256) C(512) default: return 0; }
 #undef C
