@@ -17,6 +17,10 @@
 #include "../../include/dgp.h"
 #include "dgp_internal.h"
 
+#ifndef DGP_DEPOSIT_XCD
+#define DGP_DEPOSIT_XCD 0
+#endif
+
 using namespace dgp;
 
 // ------------------------------------------------------------------ errors
@@ -201,6 +205,7 @@ struct dgp_plan {
   double* red = nullptr;             // reduction scratch
   // PM (batch 1)
   long long* grid = nullptr;         // [n3]
+  unsigned long long* copies = nullptr;   // [8][n3] per-XCD deposit copies (kept zeroed)
   double* delta = nullptr;           // [n3]
   double* mesh3 = nullptr;           // [3][n3]
   // power spectrum
@@ -340,6 +345,10 @@ static int plan_alloc(dgp_plan* pl) {
   TRY(dalloc(pl, &pl->vec, 4 * B));
   TRY(dalloc(pl, &pl->red, absmean_scratch_doubles(n3, (int)B) + 16));
   if (B == 1) {
+#if DGP_DEPOSIT_XCD
+    TRY(dalloc(pl, &pl->copies, 8 * n3));
+    HIPCHK(hipMemset(pl->copies, 0, sizeof(unsigned long long) * 8 * n3));
+#endif
     TRY(dalloc(pl, &pl->grid, n3));
     TRY(dalloc(pl, &pl->delta, n3));
     TRY(dalloc(pl, &pl->mesh3, 3 * n3));
@@ -705,8 +714,12 @@ static int require_batch1(const dgp_plan* pl) {
 static int deposit_impl(dgp_plan* pl, const void* pos, int fp32, long long np, long long* grid, double* delta,
                         bool remove_mean, hipStream_t s) {
   Timed tm(pl, s, DGP_T_DEPOSIT);
-  HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
-  launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
+  if (pl->copies) {
+    launch_deposit_xcd(pl->n, pl->box, pos, fp32, np, pl->copies, grid, s);
+  } else {
+    HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
+    launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
+  }
   if (delta) {
     launch_counts_to_delta(pl->n, grid, np, delta, s);
     if (remove_mean) {

@@ -101,6 +101,19 @@ struct RowTile {
   static constexpr int kThreads = kRW * kT;
 };
 
+// XCD-aware workgroup order.  Workgroups are dispatched round-robin over the 8 XCDs of an
+// MI355X by their linear index, and each XCD has its own L2.  Logical tiles are assigned so
+// that one XCD works through a contiguous range of them, so neighbouring tiles that share
+// 128-byte lines are fetched through the same L2.  The map is a bijection of the grid, so the
+// result does not depend on how the hardware actually dispatches.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+  const int gx = gridDim.x, g = gridDim.x * gridDim.y;
+  const int i = blockIdx.y * gx + blockIdx.x;
+  const int l = ((g & 7) == 0) ? (i & 7) * (g >> 3) + (i >> 3) : i;
+  bx = l % gx;
+  by = l / gx;
+}
+
 // ------------------------------------------------------------------ launchers
 // All launchers are asynchronous on `stream`; `done` (may be null) is a per-batch
 // flag array: work for a batch element whose flag is set is skipped.
@@ -154,6 +167,9 @@ void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, 
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
                     hipStream_t s);
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s);
+// deposit through 8 per-XCD grid copies (cleared again by the summing kernel)
+void launch_deposit_xcd(int n, double box, const void* pos, int pos_fp32, long long np, unsigned long long* copies,
+                        long long* grid, hipStream_t s);
 void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
 void launch_interp(int n, double box, const double* mesh3, const void* pos, int pos_fp32, long long np,
                    double* force, hipStream_t s);

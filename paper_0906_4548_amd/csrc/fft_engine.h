@@ -260,18 +260,30 @@ __device__ __forceinline__ void fft(cx<T> (&v)[P::R], const cx<T>* __restrict__ 
   fft_stages<T, N, P, DIR, 0, 1>(v, tw, lds, t);
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // LDS accessor for strided columns: element e of column c at base[e * C + c].
-template <typename T, int C>
+// WAVE: the transform's threads all belong to one wavefront (wave-local ordering suffices).
+template <typename T, int C, bool WAVE = false>
 struct LdsCol {
   cx<T>* base;
   int c;
   __device__ __forceinline__ cx<T> load(int e) const { return base[e * C + c]; }
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[e * C + c] = v; }
-  __device__ __forceinline__ void sync() const { __syncthreads(); }
+  __device__ __forceinline__ void sync() const {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+  }
 };
 
 // LDS accessor for contiguous rows: element e of row c at base[c * (N + N/16) + e + e/16].
-template <typename T, int N>
+// WAVE: every row is carried by lanes of a single wavefront (N/R <= 64), so the row's LDS
+// exchanges only need ordering within the wavefront, not a workgroup barrier.
+template <typename T, int N, bool WAVE = false>
 struct LdsRow {
   cx<T>* base;
   int c;
@@ -279,7 +291,10 @@ struct LdsRow {
   __device__ __forceinline__ int at(int e) const { return c * kStride + e + (e >> 4); }
   __device__ __forceinline__ cx<T> load(int e) const { return base[at(e)]; }
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[at(e)] = v; }
-  __device__ __forceinline__ void sync() const { __syncthreads(); }
+  __device__ __forceinline__ void sync() const {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+  }
 };
 
 }  // namespace dgp

@@ -22,6 +22,9 @@
 namespace dgp {
 
 // radix plan and workgroup shapes of each pass, per element type and mesh size
+#ifndef DGP_P3_WAVE_SYNC
+#define DGP_P3_WAVE_SYNC 1
+#endif
 // Plan choice per pass and element type (0: 8 elements per thread, 1: up to 16,
 // 2: 4), picked from measured pass times at 256^3 on gfx950.
 #ifndef DGP_PLAN_P1
@@ -66,9 +69,10 @@ k_p1_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restr
   constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
   const int b = blockIdx.z;
   if (batch_done(ctl, b)) return;
-  const int i1 = blockIdx.y;
+  int tile, i1;
+  xcd_tile(tile, i1);
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
-  const int i2 = (blockIdx.x * TP + c) * 2;
+  const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[N * TP];
   const T* src = in + (size_t)b * N * N * N + (size_t)i1 * N + i2;
   cx<T> v[R];
@@ -104,9 +108,10 @@ k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restr
   constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
   const int b = blockIdx.z;
   if (batch_done(ctl, b)) return;
-  const int i1 = blockIdx.y;
+  int tile, i1;
+  xcd_tile(tile, i1);
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
-  const int i2 = (blockIdx.x * TP + c) * 2;
+  const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[LSZ];
   const cx<T>* src = in + (size_t)b * H * N * N + (size_t)i1 * N + i2;
   for (int k = t; k < H; k += TT) {
@@ -159,6 +164,45 @@ k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const So
   for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
 }
 
+// Axis 1 with every column transform inside one wavefront: a wave owns WC = 64/T adjacent
+// columns (T lanes each), so radix-stage exchanges need no workgroup barrier; four waves per
+// workgroup cover 4*WC adjacent columns of the same rows.
+#ifndef DGP_P2_WAVE
+#define DGP_P2_WAVE 0
+#endif
+template <typename T, int N>
+struct WaveCol {
+  using P = Plan<N>;
+  static constexpr int R = P::R;
+  static constexpr int kT = N / R;
+  static constexpr int kWC = (64 / kT > 0) ? 64 / kT : 1;     // columns per wave
+  static constexpr int kWaves = 4;
+  static constexpr int kTY = kWC * kWaves;                      // columns per workgroup
+  static constexpr bool kOk = (kT <= 64) && (kTY <= N);
+};
+
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__(256)
+k_p2_wave(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const SolveCtl* __restrict__ ctl) {
+  using W = WaveCol<T, N>;
+  using P = typename W::P;
+  constexpr int R = W::R, TT = W::kT, WC = W::kWC, H = N / 2 + 1;
+  const int fb = blockIdx.z;
+  if (batch_done(ctl, fb % batch)) return;
+  const int k0 = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane % WC, t = lane / WC;
+  __shared__ cx<T> lds[W::kWaves * N * WC];
+  cx<T>* base = data + ((size_t)fb * H + k0) * N * N + blockIdx.x * W::kTY + wave * WC + c;
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = base[(size_t)(t + q * TT) * N];
+  LdsCol<T, WC, true> L{lds + wave * N * WC, c};
+  fft<T, N, P, DIR>(v, tw, L, t);
+#pragma unroll
+  for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
+}
+
 // ------------------------------------------------------------------ axis 2 with spectral multipliers
 struct Mode3 {
   int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
@@ -196,7 +240,8 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
   const int rr = valid ? row : 0;
   const int k0 = rr / N, k1 = rr % N;
   __shared__ cx<T> lds[RW * (N + N / 16)];
-  LdsRow<T, N> L{lds, c};
+  // a row's N/R threads are consecutive lanes; when they fit in one wavefront its exchanges are wave-local
+  LdsRow<T, N, (TT <= 64 && 64 % TT == 0 && DGP_P3_WAVE_SYNC)> L{lds, c};
   const size_t roff = (size_t)b * ROWS * N + (size_t)rr * N;
 
   cx<T> v[R];
@@ -420,6 +465,13 @@ static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, co
 }
 template <typename T, int N>
 static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  if constexpr (DGP_P2_WAVE && WaveCol<T, N>::kOk && N >= 64) {
+    using W = WaveCol<T, N>;
+    dim3 grid(N / W::kTY, N / 2 + 1, nf * batch);
+    if (dir < 0) hipLaunchKernelGGL((k_p2_wave<T, N, -1>), grid, dim3(256), 0, s, data, batch, tw, ctl);
+    else hipLaunchKernelGGL((k_p2_wave<T, N, +1>), grid, dim3(256), 0, s, data, batch, tw, ctl);
+    return;
+  }
   using G = ColTile<T, N, Geo<T, N>::P2::R>;
   dim3 grid(N / G::kTY, N / 2 + 1, nf * batch);
   if (dir < 0) hipLaunchKernelGGL((k_p2<T, N, -1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);

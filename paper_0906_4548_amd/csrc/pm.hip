@@ -37,11 +37,27 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
   return c;
 }
 
+#ifndef DGP_DEPOSIT_GROUP
+#define DGP_DEPOSIT_GROUP 64
+#endif
+// Lane -> particle map of the deposit: groups of G consecutive particles per lane group, the
+// 64/G groups of one wavefront taken from distant parts of the array, so one atomic
+// instruction spreads over 64/G cache lines instead of a few (a bijection of [0, 64 W)).
+template <int G>
+__device__ __forceinline__ long long deposit_index(long long np) {
+  const long long w = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
+  const long long waves = (np + 63) >> 6;
+  if (G >= 64) return ((long long)blockIdx.x * 256 + threadIdx.x);
+  if (w >= waves) return np;  // surplus wavefronts of the last block
+  return (long long)(l % G) + (long long)G * (w + waves * (long long)(l / G));
+}
+
 template <typename P>
 __global__ void __launch_bounds__(256)
 k_deposit(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
 #pragma clang fp contract(off)
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long p = deposit_index<DGP_DEPOSIT_GROUP>(np);
   if (p >= np) return;
   const Cic c = cic_of(pos, np, p, n, scale);
 #pragma unroll
@@ -60,6 +76,55 @@ k_deposit(const P* __restrict__ pos, long long np, int n, double scale, unsigned
         atomicAdd(&grid[(ix * n + iy) * n + iz], q);
       }
     }
+  }
+}
+
+// XCD id of the executing wave (hardware register XCC_ID, bits [3:0]); clamped to 8 copies.
+__device__ __forceinline__ int xcc_id() {
+  return int(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20)) & 7;
+}
+
+// Deposit into the private grid copy of the executing XCD with workgroup-scope atomics: every
+// workgroup of one XCD shares that XCD's L2, where the integer atomics are performed.
+template <typename P>
+__global__ void __launch_bounds__(256)
+k_deposit_xcd(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ copies) {
+#pragma clang fp contract(off)
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  const size_t n3 = (size_t)n * n * n;
+  unsigned long long* grid = copies + (size_t)xcc_id() * n3;
+  const Cic c = cic_of(pos, np, p, n, scale);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const double wx = a ? c.w1[0] : c.w0[0];
+    const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
+      const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
+        const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
+        const unsigned long long q = (unsigned long long)(long long)rint(wgt * kQScale);
+        __hip_atomic_fetch_add(&grid[(ix * n + iy) * n + iz], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    }
+  }
+}
+
+// grid = sum of the 8 copies (then the copies are cleared for the next deposit)
+__global__ void __launch_bounds__(256)
+k_sum_copies(unsigned long long* __restrict__ copies, size_t n3, long long* __restrict__ grid) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    unsigned long long s = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      s += copies[x * n3 + i];
+      copies[x * n3 + i] = 0ull;
+    }
+    grid[i] = (long long)s;
   }
 }
 
@@ -201,6 +266,19 @@ void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long 
   else
     hipLaunchKernelGGL((k_deposit<double>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const double*>(pos), np,
                        n, scale, reinterpret_cast<unsigned long long*>(grid));
+}
+
+void launch_deposit_xcd(int n, double box, const void* pos, int pos_fp32, long long np, unsigned long long* copies,
+                        long long* grid, hipStream_t s) {
+  const double scale = double(n) / box;
+  if (pos_fp32)
+    hipLaunchKernelGGL((k_deposit_xcd<float>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const float*>(pos),
+                       np, n, scale, copies);
+  else
+    hipLaunchKernelGGL((k_deposit_xcd<double>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const double*>(pos),
+                       np, n, scale, copies);
+  const size_t n3 = (size_t)n * n * n;
+  hipLaunchKernelGGL(k_sum_copies, dim3(grid_strided(n3)), dim3(256), 0, s, copies, n3, grid);
 }
 
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s) {

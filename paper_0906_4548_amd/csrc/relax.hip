@@ -70,9 +70,10 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
-  const int i1 = blockIdx.y;
+  int tile, i1;
+  xcd_tile(tile, i1);
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
-  const int i2 = (blockIdx.x * TP + c) * 2;
+  const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[LSZ];
   __shared__ double red[G::kThreads];
   __shared__ int redi[G::kThreads];
@@ -237,6 +238,256 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   }
 }
 
+// ------------------------------------------------------------------ wave-local variant
+// Same pass as k_relax, restructured so that each axis-0 transform is carried by the
+// lanes of one wavefront: its Stockham exchanges then need wavefront ordering only,
+// and the workgroup barriers drop from one pair per stage to one per field.  Global
+// traffic stays coalesced: spectral tiles are fetched row-wise into a double-buffered,
+// padded LDS tile; a transform reads its own two columns of the tile and reuses the
+// same slots (only its wavefront touches them) for the exchanges.
+#ifndef DGP_RELAX_WAVE_F64
+#define DGP_RELAX_WAVE_F64 1
+#endif
+#ifndef DGP_RELAX_WAVE_F32
+#define DGP_RELAX_WAVE_F32 0
+#endif
+
+template <typename T, int N>
+struct RelaxWGeo {
+  using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
+  static constexpr int R = P::R;
+  using G = AxisTile<T, N, R>;
+  static constexpr int kTP = G::kTP, kT = G::kT, kThreads = G::kThreads, H = N / 2 + 1;
+  static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
+  static constexpr int kTile = H * kSP;
+  static constexpr bool kWave = (kT <= 64) && (64 % kT == 0);
+  static constexpr int kNPF = (H * kTP + kThreads - 1) / kThreads;   // column pairs fetched per thread
+  static constexpr int kWaves = (kThreads + 63) / 64;
+  static constexpr int kWidth = kThreads < 64 ? kThreads : 64;       // lanes of a (possibly partial) wavefront
+  using Acc = typename RelaxGeo<T, N>::Acc;
+};
+
+// Exchange slots of transform c inside its own two tile columns (2c, 2c+1).
+template <typename T, int SP, bool WAVE>
+struct LdsPair {
+  cx<T>* base;
+  int c;
+  __device__ __forceinline__ cx<T> load(int e) const { return base[(e >> 1) * SP + 2 * c + (e & 1)]; }
+  __device__ __forceinline__ void store(int e, cx<T> v) const { base[(e >> 1) * SP + 2 * c + (e & 1)] = v; }
+  __device__ __forceinline__ void sync() const {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+  }
+};
+
+template <int W>
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+template <int W>
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__((RelaxWGeo<T, N>::kThreads))
+k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
+          cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
+          const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
+  using W = RelaxWGeo<T, N>;
+  using P = typename W::P;
+  using Acc = typename W::Acc;
+  constexpr int R = W::R, TP = W::kTP, TT = W::kT, NT = W::kThreads, H = N / 2 + 1, SP = W::kSP;
+  constexpr int NPF = W::kNPF;
+  constexpr size_t N3 = (size_t)N * N * N, NN = (size_t)N * N;
+  constexpr bool kPreload = sizeof(T) == 4;   // u and S fetched during the last transform (float only)
+  const int b = blockIdx.z;
+  if (ctl[b].done) return;
+  const int cur = ctl[b].cur, nxt = ctl[b].out;
+  int tile, i1;
+  xcd_tile(tile, i1);
+  const int i2 = tile * 2 * TP;
+  const int c = threadIdx.x / TT, t = threadIdx.x % TT;   // transform mapping
+  __shared__ cx<T> lds[2 * W::kTile];
+  __shared__ double redd[W::kWaves];
+  __shared__ int redi[W::kWaves];
+
+  const size_t col0 = (size_t)b * H * NN + (size_t)i1 * N + i2;
+  cx<T> pf[NPF][2];
+  // every thread loads NPF pairs, indices past the tile clamped to its last pair, so the
+  // staging registers are assigned unconditionally and stay in registers
+  auto fetch = [&](int f) {
+    const cx<T>* src = spec6 + f * fstride + col0;
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+      const int idx = min(int(threadIdx.x) + r * NT, H * TP - 1);
+      const int k = idx / TP, p = idx % TP;
+      const cx<T>* q = src + (size_t)k * NN + 2 * p;
+      pf[r][0] = mk(q[0].x, q[0].y);   // member-wise: a 16-byte struct copy would stay in private memory
+      pf[r][1] = mk(q[1].x, q[1].y);
+    }
+  };
+  // (a clamped index rewrites the last pair with the value it already holds)
+  auto stash = [&](cx<T>* buf) {
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+      const int idx = min(int(threadIdx.x) + r * NT, H * TP - 1);
+      const int k = idx / TP, p = idx % TP;
+      buf[k * SP + 2 * p].x = pf[r][0].x;
+      buf[k * SP + 2 * p].y = pf[r][0].y;
+      buf[k * SP + 2 * p + 1].x = pf[r][1].x;
+      buf[k * SP + 2 * p + 1].y = pf[r][1].y;
+    }
+  };
+  fetch(0);
+
+  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
+  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
+  Acc s2[R][2], h22[R][2];
+  cx<T> v[R], up[R], spv[R];
+#pragma unroll 1
+  for (int f = 0; f < 6; ++f) {
+    cx<T>* buf = lds + (f & 1) * W::kTile;
+    stash(buf);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
+      cx<T> xa, xb;
+      if (e <= N / 2) {
+        xa = buf[e * SP + 2 * c];
+        xb = buf[e * SP + 2 * c + 1];
+        if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
+      } else {
+        xa = conjg(buf[(N - e) * SP + 2 * c]);
+        xb = conjg(buf[(N - e) * SP + 2 * c + 1]);
+      }
+      v[q] = mk(xa.x - xb.y, xa.y + xb.x);
+    }
+    if (f < 5) {
+      fetch(f + 1);
+    } else if (kPreload) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const size_t off = (size_t)(t + q * TT) * NN;
+        up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
+        spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
+      }
+    }
+    LdsPair<T, SP, W::kWave> X{buf, c};
+    fft<T, N, P, +1>(v, tw, X, t);
+    if (f < 5) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Acc hx = Acc(v[q].x), hy = Acc(v[q].y);
+        if (f == 0) {
+          s2[q][0] = hx * hx;
+          s2[q][1] = hy * hy;
+          h22[q][0] = -hx;
+          h22[q][1] = -hy;
+        } else if (f == 1) {
+          s2[q][0] += hx * hx;
+          s2[q][1] += hy * hy;
+          h22[q][0] -= hx;
+          h22[q][1] -= hy;
+        } else {
+          s2[q][0] += Acc(2) * hx * hx;
+          s2[q][1] += Acc(2) * hy * hy;
+        }
+      }
+    }
+  }
+  // pointwise residual and update (v holds Nf); u^(n+1) is staged in tile 0 (free since the last barrier)
+  const double lam = cfg.lam, w = cfg.w, alpha = cfg.alpha, gamma = cfg.gamma, omega = cfg.omega;
+  const double mu = mean_u[b];
+  const double vertex = -alpha / (2.0 * (1.0 - w) * lam);
+  const double c4 = 4.0 * (1.0 - w) * lam;
+  T* ust = reinterpret_cast<T*>(lds);
+  double abs_r = 0.0;
+  int nbad = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int e = t + q * TT;
+    if (!kPreload) {
+      up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
+      spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
+    }
+    double un[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double u = double(j ? up[q].y : up[q].x);
+      const double s = double(j ? spv[q].y : spv[q].x);
+      const double nf = double(j ? v[q].y : v[q].x);
+      const double hz = double(h22[q][j]) + (u - mu);
+      const double sh2 = double(s2[q][j]) + hz * hz;
+      const double res = lam * (u * u - sh2) + alpha * u + gamma * nf - s;
+      abs_r += fabs(res);
+      const double bp = lam * (sh2 - w * u * u) - gamma * nf + s;
+      const double disc = alpha * alpha + c4 * bp;
+      double x;
+      if (disc < 0.0) {
+        x = vertex;
+        ++nbad;
+      } else {
+        x = 2.0 * bp / (alpha + sqrt(disc));
+      }
+      if (omega != 1.0) x = (1.0 - omega) * u + omega * x;
+      un[j] = x;
+    }
+    const cx<T> o = mk(T(un[0]), T(un[1]));
+    ust[e * (2 * TP + 1) + 2 * c] = o.x;
+    ust[e * (2 * TP + 1) + 2 * c + 1] = o.y;
+    v[q] = o;
+  }
+  // forward axis-0 transform of u^(n+1), exchanges in the transform's own columns of tile 1
+  {
+    LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
+    fft<T, N, P, -1>(v, tw, X, t);
+  }
+  abs_r = wave_sum<W::kWidth>(abs_r);
+  nbad = wave_sum<W::kWidth>(nbad);
+  if ((threadIdx.x & 63) == 0) {
+    redd[threadIdx.x >> 6] = abs_r;
+    redi[threadIdx.x >> 6] = nbad;
+  }
+  __syncthreads();
+  // u^(n+1) out of tile 0 (coalesced); the spectrum into tile 1, column-major with one pad
+  T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+  for (int idx = threadIdx.x; idx < N * TP; idx += NT) {
+    const int e = idx / TP, p = idx % TP;
+    const cx<T> o = mk(ust[e * (2 * TP + 1) + 2 * p], ust[e * (2 * TP + 1) + 2 * p + 1]);
+    *reinterpret_cast<cx<T>*>(uout + (size_t)e * NN + 2 * p) = o;
+  }
+  cx<T>* zt = lds + W::kTile;
+#pragma unroll
+  for (int q = 0; q < R; ++q) zt[c * (N + 1) + t + q * TT] = v[q];
+  __syncthreads();
+  cx<T>* dst = spec_u + col0;
+  for (int idx = threadIdx.x; idx < H * TP; idx += NT) {
+    const int k = idx / TP, p = idx % TP;
+    const cx<T> zk = zt[p * (N + 1) + k];
+    const cx<T> zn = zt[p * (N + 1) + ((N - k) & (N - 1))];
+    dst[(size_t)k * NN + 2 * p] = mk(T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y));
+    dst[(size_t)k * NN + 2 * p + 1] = mk(T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x));
+  }
+  if (threadIdx.x == 0) {
+    double sr = 0.0;
+    int sb = 0;
+    for (int i = 0; i < W::kWaves; ++i) {
+      sr += redd[i];
+      sb += redi[i];
+    }
+    const size_t g = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const size_t groups = (size_t)gridDim.x * gridDim.y;
+    partial[((size_t)b * groups + g) * 2] = sr;
+    partial[((size_t)b * groups + g) * 2 + 1] = double(sb);
+  }
+}
+
 // Convergence control: one workgroup of 256 threads walks the batch.
 __global__ void __launch_bounds__(256)
 k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict__ ctl, SolveCfg cfg,
@@ -372,8 +623,14 @@ static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u,
   using G = typename RelaxGeo<T, N>::G;
   constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
   dim3 grid(N / (2 * G::kTP), N, batch);
-  hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
-                     partial, mean_u, cfg, ctl, twiddles<T>(N));
+  if constexpr ((sizeof(T) == 8 ? DGP_RELAX_WAVE_F64 : DGP_RELAX_WAVE_F32) && RelaxWGeo<T, N>::kWave) {
+    static_assert(RelaxWGeo<T, N>::kTP == G::kTP, "tile geometry shared with relax_groups");
+    hipLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield,
+                       spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
+  } else {
+    hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
+                       partial, mean_u, cfg, ctl, twiddles<T>(N));
+  }
 }
 
 template <typename T>
