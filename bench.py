@@ -6,7 +6,14 @@ field, P(k) ~ k^-1.5 exp(-k^2/k_c^2), k_c = 1 h/Mpc, rms displacement 2 Mpc/h),
 z = 1 (a = 0.5), Omega_m0 = 0.27, w = 1/3.  One step = CIC deposit -> field solve
 from the linear guess to normalised residual 1e-8 -> modified-Poisson forces ->
 CIC interpolation + leapfrog kick-drift.  Inputs are resident on the GPU before
-the timed region; particles advance from step to step.
+the timed region; particles advance from step to step.  Particles are stored in
+Lagrangian blocks of 8^3 (a spatially coherent order, as a PM code keeps them).
+
+Other modes:
+  --probe                 a short run for hardware-counter passes (two precision-form
+                          steps plus a plain 512 MiB device copy for calibration)
+  --pmc-summary F W       turn the counter CSVs of two such passes (FETCH_SIZE, then
+                          WRITE_SIZE) into the traffic summary kept under profiles/
 
 The solve runs in the precision form (float32 FFTs and pointwise storage,
 float64 residual / discriminant / root / reductions, float64 polish); the plain
@@ -16,6 +23,9 @@ value = field-solve cells*iterations per second over whole PM steps:
 N^3 x (relaxation passes executed) / (step wall time).  One JSON line on stdout.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -33,6 +43,119 @@ TOL = 1e-8
 RNL = 1.78          # nonlinear ratio lambda max|u_lin| / alpha (screened; see the design doc for the choice)
 DLNA = 0.005
 PEAK_HBM = 8.0e12   # bytes/s, MI355X
+BLOCK = 8           # particles stored in Lagrangian blocks of BLOCK^3
+COPY_BYTES = 512 * 1024 * 1024   # calibration copy of the probe: reads and writes this many bytes
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_pm_step_256.md")
+# timing class of the library -> device kernel names (prefixes) it launches
+CLASS_KERNELS = {
+    "relax_fp32": ("dgp::k_relax<float, 256>", "dgp::k_relax_w<float, 256>"),
+    "relax": ("dgp::k_relax<double, 256>", "dgp::k_relax_w<double, 256>"),
+    "deposit": ("dgp::k_deposit_bin<double>", "dgp::k_deposit<double>"),
+}
+
+
+def kernel_source_digest():
+    """sha256 over the device sources: counter figures are valid only for the code they measured."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_0906_4548_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_name(sig):
+    """'void dgp::k<T, 256>(args...)' -> 'dgp::k<T, 256>'."""
+    sig = sig.strip()
+    if sig.startswith("void "):
+        sig = sig[5:]
+    if sig.endswith(")"):
+        depth = 0
+        for i in range(len(sig) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(sig[i], 0)
+            if depth == 0:
+                return sig[:i]
+    return sig
+
+
+def read_counters(path):
+    """rocprofv3 counter_collection CSV -> {kernel name: [values in bytes per dispatch]}."""
+    out = {}
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            name = kernel_name(row.get("Kernel_Name") or row.get("Kernel-Name") or "")
+            val = float(row.get("Counter_Value") or row.get("Counter-Value") or 0.0)
+            out.setdefault(name, []).append(val * 1024.0)   # FETCH_SIZE / WRITE_SIZE count KiB
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Markdown summary of HBM traffic per dispatch, calibrated on the probe's plain copy."""
+    fetch, write = read_counters(fetch_csv), read_counters(write_csv)
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    big = [k for k in copy if max(fetch[k]) > 0.25 * COPY_BYTES]
+    if not big:
+        raise SystemExit("no calibration copy kernel found in %s" % fetch_csv)
+    ck = big[0]
+    f_scale = COPY_BYTES / max(fetch[ck])
+    w_scale = COPY_BYTES / max(write.get(ck, [COPY_BYTES]))
+    rows, table = {}, []
+    for name in sorted(fetch):
+        if not name.startswith("dgp::"):
+            continue
+        f = sum(fetch[name]) / len(fetch[name]) * f_scale
+        w = (sum(write[name]) / len(write[name]) * w_scale) if name in write else None
+        rows[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches": len(fetch[name])}
+        table.append("| `%s` | %d | %.1f | %s |" % (name, len(fetch[name]), f / 2 ** 20,
+                                                    "%.1f" % (w / 2 ** 20) if w is not None else "-"))
+    lines = [
+        "# HBM traffic per dispatch: PM step at 256^3 (FETCH_SIZE / WRITE_SIZE, calibrated)",
+        "",
+        "Commands (repository root `$R`, one MI355X; one counter per pass):",
+        "",
+        "    cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o run -- "
+        "python3 $R/bench.py --probe",
+        "    cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o run -- "
+        "python3 $R/bench.py --probe",
+        "    python3 bench.py --pmc-summary <pmc_fetch>/run_counter_collection.csv "
+        "<pmc_write>/run_counter_collection.csv",
+        "",
+        "Calibration: the probe's plain copy `%s` moves %d MiB each way; its raw counters read "
+        "%.1f MiB fetched and %.1f MiB written, so fetch values are scaled by %.3f and write values by %.3f."
+        % (ck, COPY_BYTES // 2 ** 20, max(fetch[ck]) / 2 ** 20, max(write.get(ck, [0.0])) / 2 ** 20, f_scale, w_scale),
+        "",
+        "| kernel | dispatches | fetch MiB/dispatch | write MiB/dispatch |",
+        "|---|---:|---:|---:|",
+    ] + table + [
+        "",
+        "Machine-readable copy (bench.py reports `roofline.traffic` from it while the device sources "
+        "still hash to `source_sha256`):",
+        "",
+        "```json",
+        json.dumps({"source_sha256": kernel_source_digest(), "kernels": rows}, indent=1),
+        "```",
+        "",
+    ]
+    return "\n".join(lines)
+
+
+def stored_traffic(cls):
+    """Calibrated HBM bytes per dispatch of the kernel behind timing class `cls`, or None when
+    no summary exists or the device sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != kernel_source_digest():
+        return None
+    for name in CLASS_KERNELS.get(cls, ()):
+        k = blob["kernels"].get(name)
+        if k and k.get("write_bytes") is not None:
+            return k["fetch_bytes"] + k["write_bytes"]
+    return None
 
 
 def algorithmic_bytes(cls, n, elem):
@@ -55,7 +178,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain float64 comparison")
+    ap.add_argument("--probe", action="store_true", help="short run for hardware-counter passes")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the calibrated traffic summary from two counter passes to stdout")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(pmc_summary(*args.pmc_summary))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the field solve is built for a single MI355X "
               "(multi-GPU sharding is a design note, not part of this build); use --gpus 1", file=sys.stderr)
@@ -67,7 +196,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     print("bench: building inputs", file=sys.stderr, flush=True)
-    pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED)
+    pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED, block=BLOCK)
     npart = pos_h.shape[1]
     pos0 = torch.from_numpy(pos_h).to(dev)
     prm0 = dgp.params(OM0, A)
@@ -106,6 +235,17 @@ def main():
         plan.close()
         return dt, infos, tim
 
+    if args.probe:
+        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        run_form(dgp.FP32, 2, 0)
+        torch.cuda.synchronize()
+        print("probe done", file=sys.stderr, flush=True)
+        return
+
     print("bench: timing precision form", file=sys.stderr, flush=True)
     dt32, infos32, tim32 = run_form(dgp.FP32, args.steps, args.warmup)
     passes32 = sum(i["passes"] for _, i in infos32)
@@ -143,7 +283,7 @@ def main():
     bpl = algorithmic_bytes(base, N, elem)
     avg_s = tim32[dom][0] / tim32[dom][1] * 1e-3
     res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": bpl / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
-                       "unit": "GB/s", "frac": bpl / avg_s / PEAK_HBM, "traffic": None,
+                       "unit": "GB/s", "frac": bpl / avg_s / PEAK_HBM, "traffic": stored_traffic(dom),
                        "bytes_per_launch": bpl, "avg_us": avg_s * 1e6}
     gbs = {}
     for k, (ms, cnt) in tim32.items():

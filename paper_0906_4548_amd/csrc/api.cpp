@@ -17,9 +17,6 @@
 #include "../../include/dgp.h"
 #include "dgp_internal.h"
 
-#ifndef DGP_DEPOSIT_XCD
-#define DGP_DEPOSIT_XCD 0
-#endif
 
 using namespace dgp;
 
@@ -205,7 +202,6 @@ struct dgp_plan {
   double* red = nullptr;             // reduction scratch
   // PM (batch 1)
   long long* grid = nullptr;         // [n3]
-  unsigned long long* copies = nullptr;   // [8][n3] per-XCD deposit copies (kept zeroed)
   double* delta = nullptr;           // [n3]
   double* mesh3 = nullptr;           // [3][n3]
   // power spectrum
@@ -345,10 +341,6 @@ static int plan_alloc(dgp_plan* pl) {
   TRY(dalloc(pl, &pl->vec, 4 * B));
   TRY(dalloc(pl, &pl->red, absmean_scratch_doubles(n3, (int)B) + 16));
   if (B == 1) {
-#if DGP_DEPOSIT_XCD
-    TRY(dalloc(pl, &pl->copies, 8 * n3));
-    HIPCHK(hipMemset(pl->copies, 0, sizeof(unsigned long long) * 8 * n3));
-#endif
     TRY(dalloc(pl, &pl->grid, n3));
     TRY(dalloc(pl, &pl->delta, n3));
     TRY(dalloc(pl, &pl->mesh3, 3 * n3));
@@ -648,28 +640,40 @@ extern "C" int dgp_solve_field(dgp_plan* pl, const dgp_params* p, const double* 
 }
 
 // ------------------------------------------------------------------ precision form: float32 passes + float64 polish
+#ifndef DGP_SWITCH_TOL
+#define DGP_SWITCH_TOL 1e-6
+#endif
+#ifndef DGP_SWITCH_HANDOFF
+#define DGP_SWITCH_HANDOFF 1
+#endif
 // Phase 1 runs float32 relaxation passes (float64 pointwise arithmetic and
-// reductions) from the linear guess until the float32 residual reaches
-// max(tol, switch_tol) or stalls; phase 2 continues with float64 passes from that
-// iterate until the float64 residual meets tol.  The returned residual is
-// always a float64 evaluation.
+// reductions) from the initial guess until the float32 residual reaches
+// max(tol, switch_tol) (or phase 1 ends on max_iter or bad points); phase 2
+// continues with float64 passes, from the update that the last float32 pass
+// computed, until the float64 residual meets tol.  The returned residual is always
+// a float64 evaluation.
 int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
                    hipStream_t s) {
   const int B = pl->batch;
   const size_t n3 = pl->n3;
   Ws<float> w32 = ws32(pl);
-  // float32 copies of delta
-  launch_convert<float>(B * n3, delta, 0, w32.U + 2 * B * n3, s);   // use the third buffer as scratch
-  TRY(setup_source<float>(pl, p, w32.U + 2 * B * n3, w32, p->init == DGP_INIT_LINEAR, s));
-  if (p->init == DGP_INIT_WARM) {
+  Ws<double> w = ws64(pl);
+  // the source (and the linear guess) are formed once in float64: phase 2 needs them
+  // exact, and phase 1 takes their rounding, which is closer than a float32 evaluation
+  TRY(setup_source<double>(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
+  launch_convert<float>(B * n3, w.S, 0, w32.S, s);
+  if (p->init == DGP_INIT_LINEAR) {
+    launch_convert<float>(B * n3, w.U, 0, w32.U, s);
+  } else if (p->init == DGP_INIT_WARM) {
     launch_convert<float>(B * n3, u_state, 0, w32.U, s);
-  } else if (p->init == DGP_INIT_ZERO) {
+  } else {
     HIPCHK(hipMemsetAsync(w32.U, 0, sizeof(float) * B * n3, s));
   }
-  launch_absmean<float>(n3, w32.S, B, pl->red, pl->vec, nullptr, s);
+  // eps = <|S|> of the float64 source; it stays in pl->vec for both phases
+  launch_absmean<double>(n3, w.S, B, pl->red, pl->vec, nullptr, s);
   launch_ctl_init(pl->ctl, pl->vec, B, s);
   launch_p1_fwd<float>(pl->n, w32.U, w32.spec_u, B, nullptr, s);
-  const double switch_tol = std::max(p->tol, 1e-6);
+  const double switch_tol = std::max(p->tol, double(DGP_SWITCH_TOL));
   SolveCfg cfg32 = solve_cfg(pl, p, switch_tol, p->max_iter);
   int passes32 = 0;
   TRY(run_loop<float>(pl, p, w32, cfg32, s, &passes32));
@@ -679,14 +683,14 @@ int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
   std::vector<int> p32(B), it32(B);
   for (int b = 0; b < B; ++b) {
     const SolveCtl& C = pl->ctl_host[b];
-    launch_convert<double>(n3, w32.U + ((size_t)C.result * B + b) * n3, 1, pl->U + (size_t)b * n3, s);
+    // warm start: the update computed by the pass that met the switch tolerance (one
+    // relaxation step past the checked iterate) unless that update met bad points
+    const int src = (DGP_SWITCH_HANDOFF && C.status == 0 && C.final_bad == 0) ? C.out : C.result;
+    launch_convert<double>(n3, w32.U + ((size_t)src * B + b) * n3, 1, pl->U + (size_t)b * n3, s);
     p32[b] = C.passes;
-    it32[b] = C.iters;
+    it32[b] = C.iters + (src == C.out ? 1 : 0);
   }
   LAUNCHCHK();
-  Ws<double> w = ws64(pl);
-  TRY(setup_source<double>(pl, p, delta, w, false, s));
-  launch_absmean<double>(n3, w.S, B, pl->red, pl->vec, nullptr, s);
   launch_ctl_init(pl->ctl, pl->vec, B, s);
   launch_p1_fwd<double>(pl->n, w.U, w.spec_u, B, nullptr, s);
   const int left = std::max(0, p->max_iter - *std::min_element(it32.begin(), it32.end()));
@@ -714,12 +718,8 @@ static int require_batch1(const dgp_plan* pl) {
 static int deposit_impl(dgp_plan* pl, const void* pos, int fp32, long long np, long long* grid, double* delta,
                         bool remove_mean, hipStream_t s) {
   Timed tm(pl, s, DGP_T_DEPOSIT);
-  if (pl->copies) {
-    launch_deposit_xcd(pl->n, pl->box, pos, fp32, np, pl->copies, grid, s);
-  } else {
-    HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
-    launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
-  }
+  HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
+  launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
   if (delta) {
     launch_counts_to_delta(pl->n, grid, np, delta, s);
     if (remove_mean) {

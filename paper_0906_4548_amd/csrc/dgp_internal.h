@@ -56,6 +56,7 @@ struct SolveCtl {
   int bad_seen;
   int passes;       // residual evaluations executed
   int last_bad;     // bad points of the last update
+  int final_bad;    // bad points of the update computed by the pass that met tol (-1: none)
   double eps;       // <|S|>
   double resid;     // r of the returned iterate
   double resid_min;
@@ -167,9 +168,6 @@ void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, 
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
                     hipStream_t s);
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s);
-// deposit through 8 per-XCD grid copies (cleared again by the summing kernel)
-void launch_deposit_xcd(int n, double box, const void* pos, int pos_fp32, long long np, unsigned long long* copies,
-                        long long* grid, hipStream_t s);
 void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
 void launch_interp(int n, double box, const double* mesh3, const void* pos, int pos_fp32, long long np,
                    double* force, hipStream_t s);

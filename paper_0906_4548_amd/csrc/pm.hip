@@ -37,27 +37,11 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
   return c;
 }
 
-#ifndef DGP_DEPOSIT_GROUP
-#define DGP_DEPOSIT_GROUP 64
-#endif
-// Lane -> particle map of the deposit: groups of G consecutive particles per lane group, the
-// 64/G groups of one wavefront taken from distant parts of the array, so one atomic
-// instruction spreads over 64/G cache lines instead of a few (a bijection of [0, 64 W)).
-template <int G>
-__device__ __forceinline__ long long deposit_index(long long np) {
-  const long long w = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
-  const int l = threadIdx.x & 63;
-  const long long waves = (np + 63) >> 6;
-  if (G >= 64) return ((long long)blockIdx.x * 256 + threadIdx.x);
-  if (w >= waves) return np;  // surplus wavefronts of the last block
-  return (long long)(l % G) + (long long)G * (w + waves * (long long)(l / G));
-}
-
 template <typename P>
 __global__ void __launch_bounds__(256)
 k_deposit(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
 #pragma clang fp contract(off)
-  const long long p = deposit_index<DGP_DEPOSIT_GROUP>(np);
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= np) return;
   const Cic c = cic_of(pos, np, p, n, scale);
 #pragma unroll
@@ -79,52 +63,149 @@ k_deposit(const P* __restrict__ pos, long long np, int n, double scale, unsigned
   }
 }
 
-// XCD id of the executing wave (hardware register XCC_ID, bits [3:0]); clamped to 8 copies.
-__device__ __forceinline__ int xcc_id() {
-  return int(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20)) & 7;
+// Binned deposit.  A workgroup takes a chunk of consecutive particles, finds the
+// periodic bounding box of their CIC cells and, when the box fits the LDS histogram,
+// sums the chunk's quantised weights there with LDS atomics and then adds each
+// non-zero box cell to the mesh with one global atomic.  Integer sums make the result
+// identical to the direct deposit in any order; the gain needs spatially coherent
+// chunks (particles stored in compact Lagrangian blocks).  A chunk whose box is too
+// large takes the direct per-particle atomics.
+#ifndef DGP_DEPOSIT_CHUNK
+#define DGP_DEPOSIT_CHUNK 512
+#endif
+#ifndef DGP_DEPOSIT_BIN_CAP
+#define DGP_DEPOSIT_BIN_CAP 2048
+#endif
+constexpr int kDepChunk = DGP_DEPOSIT_CHUNK;   // particles per workgroup
+constexpr int kDepPPT = kDepChunk / 256;       // particles per thread
+constexpr int kBinCap = DGP_DEPOSIT_BIN_CAP;   // cells of the LDS histogram
+static_assert(kDepChunk % 256 == 0, "chunk must be a multiple of the workgroup size");
+
+// offset of cell i from the reference cell r on a periodic axis of n cells, in [-n/2, n/2)
+__device__ __forceinline__ int periodic_offset(int i, int r, int n) {
+  int o = i - r;
+  if (o < -n / 2) o += n;
+  if (o >= n / 2) o -= n;
+  return o;
 }
 
-// Deposit into the private grid copy of the executing XCD with workgroup-scope atomics: every
-// workgroup of one XCD shares that XCD's L2, where the integer atomics are performed.
-template <typename P>
-__global__ void __launch_bounds__(256)
-k_deposit_xcd(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ copies) {
-#pragma clang fp contract(off)
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= np) return;
-  const size_t n3 = (size_t)n * n * n;
-  unsigned long long* grid = copies + (size_t)xcc_id() * n3;
-  const Cic c = cic_of(pos, np, p, n, scale);
+// Periodic bounding box of a chunk's CIC base cells, relative to the base cell cr of its
+// first particle: offsets in [-n/2, n/2) per axis, box lo[d] .. lo[d] + ext[d] - 1 (the
+// +1 corners included).  Returns true when the box volume is at most `cap`.  Every
+// thread of the (256-thread) workgroup must call it.
+template <int PPT, typename P>
+__device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, long long np, int n, double scale, long long p0,
+                                          int cap, Cic& cr, Cic (&cs)[PPT], int (&off)[PPT][3], int (&bx)[6]) {
+  __shared__ int wlo[4][3], whi[4][3];
+  __shared__ int sbox[7];
+  cr = cic_of(pos, np, p0, n, scale);
+  int lo[3] = {n, n, n}, hi[3] = {-n, -n, -n};
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const double wx = a ? c.w1[0] : c.w0[0];
-    const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
+  for (int k = 0; k < PPT; ++k) {
+    const long long p = p0 + threadIdx.x + k * 256;
+    if (p < np) {
+      cs[k] = cic_of(pos, np, p, n, scale);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
-      const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
-        const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
-        const unsigned long long q = (unsigned long long)(long long)rint(wgt * kQScale);
-        __hip_atomic_fetch_add(&grid[(ix * n + iy) * n + iz], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (int d = 0; d < 3; ++d) {
+        off[k][d] = periodic_offset(cs[k].i0[d], cr.i0[d], n);
+        lo[d] = min(lo[d], off[k][d]);
+        hi[d] = max(hi[d], off[k][d] + 1);
       }
     }
   }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      wlo[threadIdx.x >> 6][d] = lo[d];
+      whi[threadIdx.x >> 6][d] = hi[d];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long vol = 1;
+    for (int d = 0; d < 3; ++d) {
+      int l = wlo[0][d], h = whi[0][d];
+      for (int w = 1; w < 4; ++w) {
+        l = min(l, wlo[w][d]);
+        h = max(h, whi[w][d]);
+      }
+      sbox[d] = l;
+      sbox[3 + d] = h - l + 1;
+      vol *= h - l + 1;
+    }
+    sbox[6] = vol <= cap ? 1 : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int d = 0; d < 6; ++d) bx[d] = sbox[d];
+  return sbox[6] != 0;
 }
 
-// grid = sum of the 8 copies (then the copies are cleared for the next deposit)
+// mesh index of box cell i (row-major over the box extents), wrapped onto the periodic mesh
+__device__ __forceinline__ size_t box_cell(int i, const Cic& cr, const int (&bx)[6], int n) {
+  const int plane = bx[4] * bx[5];
+  const int x = i / plane, r = i - x * plane;
+  const int y = r / bx[5], z = r - y * bx[5];
+  const size_t gx = (size_t)(((cr.i0[0] + bx[0] + x) % n + n) % n);
+  const size_t gy = (size_t)(((cr.i0[1] + bx[1] + y) % n + n) % n);
+  const size_t gz = (size_t)(((cr.i0[2] + bx[2] + z) % n + n) % n);
+  return (gx * n + gy) * n + gz;
+}
+
+template <typename P>
 __global__ void __launch_bounds__(256)
-k_sum_copies(unsigned long long* __restrict__ copies, size_t n3, long long* __restrict__ grid) {
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
-    unsigned long long s = 0;
+k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
+#pragma clang fp contract(off)
+  __shared__ unsigned long long hist[kBinCap];
+  const long long p0 = (long long)blockIdx.x * kDepChunk;
+  Cic cr, cs[kDepPPT];
+  int off[kDepPPT][3], bx[6];
+  const bool binned = chunk_box<kDepPPT>(pos, np, n, scale, p0, kBinCap, cr, cs, off, bx);
+  const int vol = bx[3] * bx[4] * bx[5];
+  if (binned)
+    for (int i = threadIdx.x; i < vol; i += 256) hist[i] = 0ull;
+  __syncthreads();
 #pragma unroll
-    for (int x = 0; x < 8; ++x) {
-      s += copies[x * n3 + i];
-      copies[x * n3 + i] = 0ull;
+  for (int k = 0; k < kDepPPT; ++k) {
+    const long long p = p0 + threadIdx.x + k * 256;
+    if (p >= np) continue;
+    const Cic& c = cs[k];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double wx = a ? c.w1[0] : c.w0[0];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+          const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
+          const unsigned long long q = (unsigned long long)(long long)rint(wgt * kQScale);
+          if (binned) {
+            const int li = ((off[k][0] + a - bx[0]) * bx[4] + (off[k][1] + b - bx[1])) * bx[5] + (off[k][2] + cc - bx[2]);
+            atomicAdd(&hist[li], q);
+          } else {
+            const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
+            const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
+            const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
+            atomicAdd(&grid[(ix * n + iy) * n + iz], q);
+          }
+        }
+      }
     }
-    grid[i] = (long long)s;
+  }
+  if (!binned) return;
+  __syncthreads();
+  for (int i = threadIdx.x; i < vol; i += 256) {
+    const unsigned long long v = hist[i];
+    if (v != 0ull) atomicAdd(&grid[box_cell(i, cr, bx, n)], v);
   }
 }
 
@@ -145,29 +226,42 @@ k_sub_mean(double* __restrict__ x, size_t n3, const double* __restrict__ mean) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) xb[i] -= m;
 }
 
-// interpolate a 3-component mesh [3][N^3] to particles
-template <typename P>
-__device__ __forceinline__ void gather3(const double* __restrict__ mesh3, size_t n3, int n, const Cic& c,
-                                        double (&f)[3]) {
+// CIC interpolation of a 3-component field: f[k] = sum over the 8 corners of
+// (w_x w_y) w_z times the corner value of component k; `at(a, b, c, k)` reads the value.
+template <class At>
+__device__ __forceinline__ void gather_corners(const Cic& c, const At& at, double (&f)[3]) {
+#pragma clang fp contract(off)
   f[0] = f[1] = f[2] = 0.0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const double wx = a ? c.w1[0] : c.w0[0];
-    const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
-      const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
         const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
-        const size_t idx = (ix * n + iy) * n + (size_t)(cc ? c.i1[2] : c.i0[2]);
-        f[0] += wgt * mesh3[idx];
-        f[1] += wgt * mesh3[n3 + idx];
-        f[2] += wgt * mesh3[2 * n3 + idx];
+        f[0] += wgt * at(a, b, cc, 0);
+        f[1] += wgt * at(a, b, cc, 1);
+        f[2] += wgt * at(a, b, cc, 2);
       }
     }
   }
+}
+
+// interpolate a 3-component mesh [3][N^3] to particles
+template <typename P>
+__device__ __forceinline__ void gather3(const double* __restrict__ mesh3, size_t n3, int n, const Cic& c,
+                                        double (&f)[3]) {
+  gather_corners(
+      c,
+      [&](int a, int b, int cc, int k) {
+        const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
+        const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
+        const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
+        return mesh3[(size_t)k * n3 + (ix * n + iy) * n + iz];
+      },
+      f);
 }
 
 template <typename P>
@@ -205,6 +299,71 @@ k_interp_kick_drift(const double* __restrict__ mesh3, P* __restrict__ pos, P* __
     if (xo >= P(box)) xo = xo - P(box);
     vel[k] = P(v);
     pos[k] = xo;
+  }
+}
+
+// Kick-drift with the force mesh of the chunk's box staged in LDS (coalesced rows), the
+// chunking of the binned deposit (smaller chunks: three components per cell in LDS);
+// chunks with larger boxes gather from the mesh.
+#ifndef DGP_GATHER_CHUNK
+#define DGP_GATHER_CHUNK 256
+#endif
+#ifndef DGP_GATHER_BIN_CAP
+#define DGP_GATHER_BIN_CAP 1024
+#endif
+constexpr int kGatherChunk = DGP_GATHER_CHUNK;
+constexpr int kGatherPPT = kGatherChunk / 256;
+constexpr int kGatherCap = DGP_GATHER_BIN_CAP;
+static_assert(kGatherChunk % 256 == 0, "chunk must be a multiple of the workgroup size");
+
+template <typename P>
+__global__ void __launch_bounds__(256)
+k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
+                        int n, double scale, double box, double kick, double drift) {
+#pragma clang fp contract(off)
+  __shared__ double fl[3 * kGatherCap];
+  const size_t n3 = (size_t)n * n * n;
+  const long long p0 = (long long)blockIdx.x * kGatherChunk;
+  Cic cr, cs[kGatherPPT];
+  int off[kGatherPPT][3], bx[6];
+  const bool binned = chunk_box<kGatherPPT>(pos, np, n, scale, p0, kGatherCap, cr, cs, off, bx);
+  if (binned) {
+    const int vol = bx[3] * bx[4] * bx[5];
+    for (int i = threadIdx.x; i < vol; i += 256) {
+      const size_t g = box_cell(i, cr, bx, n);
+      fl[i] = mesh3[g];
+      fl[kGatherCap + i] = mesh3[n3 + g];
+      fl[2 * kGatherCap + i] = mesh3[2 * n3 + g];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kGatherPPT; ++k) {
+    const long long p = p0 + threadIdx.x + k * 256;
+    if (p >= np) continue;
+    double f[3];
+    if (binned) {
+      gather_corners(
+          cs[k],
+          [&](int a, int b, int cc, int q) {
+            const int li = ((off[k][0] + a - bx[0]) * bx[4] + (off[k][1] + b - bx[1])) * bx[5] + (off[k][2] + cc - bx[2]);
+            return fl[q * kGatherCap + li];
+          },
+          f);
+    } else {
+      gather3<P>(mesh3, n3, n, cs[k], f);
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const size_t i = (size_t)d * np + p;
+      const double v = double(vel[i]) + kick * f[d];
+      double x = double(pos[i]) + drift * v;
+      x = x - box * floor(x / box);
+      P xo = P(x);
+      if (xo >= P(box)) xo = xo - P(box);
+      vel[i] = P(v);
+      pos[i] = xo;
+    }
   }
 }
 
@@ -258,28 +417,30 @@ static unsigned grid_strided(size_t count) {
   return unsigned(g > 8192 ? 8192 : (g < 1 ? 1 : g));
 }
 
+#ifndef DGP_DEPOSIT_BINNED
+#define DGP_DEPOSIT_BINNED 1
+#endif
+
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid, hipStream_t s) {
   const double scale = double(n) / box;
-  if (pos_fp32)
+  auto* out = reinterpret_cast<unsigned long long*>(grid);
+  if (DGP_DEPOSIT_BINNED) {
+    const unsigned g = unsigned((np + kDepChunk - 1) / kDepChunk);
+    if (pos_fp32)
+      hipLaunchKernelGGL((k_deposit_bin<float>), dim3(g), dim3(256), 0, s, static_cast<const float*>(pos), np, n,
+                         scale, out);
+    else
+      hipLaunchKernelGGL((k_deposit_bin<double>), dim3(g), dim3(256), 0, s, static_cast<const double*>(pos), np, n,
+                         scale, out);
+  } else if (pos_fp32) {
     hipLaunchKernelGGL((k_deposit<float>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const float*>(pos), np, n,
-                       scale, reinterpret_cast<unsigned long long*>(grid));
-  else
+                       scale, out);
+  } else {
     hipLaunchKernelGGL((k_deposit<double>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const double*>(pos), np,
-                       n, scale, reinterpret_cast<unsigned long long*>(grid));
+                       n, scale, out);
+  }
 }
 
-void launch_deposit_xcd(int n, double box, const void* pos, int pos_fp32, long long np, unsigned long long* copies,
-                        long long* grid, hipStream_t s) {
-  const double scale = double(n) / box;
-  if (pos_fp32)
-    hipLaunchKernelGGL((k_deposit_xcd<float>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const float*>(pos),
-                       np, n, scale, copies);
-  else
-    hipLaunchKernelGGL((k_deposit_xcd<double>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const double*>(pos),
-                       np, n, scale, copies);
-  const size_t n3 = (size_t)n * n * n;
-  hipLaunchKernelGGL(k_sum_copies, dim3(grid_strided(n3)), dim3(256), 0, s, copies, n3, grid);
-}
 
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s) {
   const size_t n3 = (size_t)n * n * n;
@@ -302,9 +463,23 @@ void launch_interp(int n, double box, const double* mesh3, const void* pos, int 
                        static_cast<const double*>(pos), np, n, scale, force);
 }
 
+#ifndef DGP_GATHER_BINNED
+#define DGP_GATHER_BINNED 1
+#endif
+
 void launch_interp_kick_drift(int n, double box, const double* mesh3, void* pos, void* vel, int fp32, long long np,
                               double kick, double drift, hipStream_t s) {
   const double scale = double(n) / box;
+  if (DGP_GATHER_BINNED) {
+    const unsigned g = unsigned((np + kGatherChunk - 1) / kGatherChunk);
+    if (fp32)
+      hipLaunchKernelGGL((k_interp_kick_drift_bin<float>), dim3(g), dim3(256), 0, s, mesh3, static_cast<float*>(pos),
+                         static_cast<float*>(vel), np, n, scale, box, kick, drift);
+    else
+      hipLaunchKernelGGL((k_interp_kick_drift_bin<double>), dim3(g), dim3(256), 0, s, mesh3,
+                         static_cast<double*>(pos), static_cast<double*>(vel), np, n, scale, box, kick, drift);
+    return;
+  }
   if (fp32)
     hipLaunchKernelGGL((k_interp_kick_drift<float>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
                        static_cast<float*>(pos), static_cast<float*>(vel), np, n, scale, box, kick, drift);

@@ -245,11 +245,30 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 // traffic stays coalesced: spectral tiles are fetched row-wise into a double-buffered,
 // padded LDS tile; a transform reads its own two columns of the tile and reuses the
 // same slots (only its wavefront touches them) for the exchanges.
-#ifndef DGP_RELAX_WAVE_F64
-#define DGP_RELAX_WAVE_F64 1
+#ifndef DGP_RELAXW_WAVE_F64
+#define DGP_RELAXW_WAVE_F64 1
 #endif
-#ifndef DGP_RELAX_WAVE_F32
-#define DGP_RELAX_WAVE_F32 0
+#ifndef DGP_RELAXW_WAVE_F32
+#define DGP_RELAXW_WAVE_F32 0
+#endif
+
+#ifndef DGP_RELAXW_TP_F32
+#define DGP_RELAXW_TP_F32 0
+#endif
+#ifndef DGP_RELAXW_TP_F64
+#define DGP_RELAXW_TP_F64 0
+#endif
+#ifndef DGP_RELAXW_MINB_F32
+#define DGP_RELAXW_MINB_F32 1
+#endif
+#ifndef DGP_RELAXW_MINB_F64
+#define DGP_RELAXW_MINB_F64 3
+#endif
+#ifndef DGP_RELAXW_PRELOAD
+#define DGP_RELAXW_PRELOAD 1
+#endif
+#ifndef DGP_RELAXW_XBUF
+#define DGP_RELAXW_XBUF 0
 #endif
 
 template <typename T, int N>
@@ -257,7 +276,12 @@ struct RelaxWGeo {
   using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
   static constexpr int R = P::R;
   using G = AxisTile<T, N, R>;
-  static constexpr int kTP = G::kTP, kT = G::kT, kThreads = G::kThreads, H = N / 2 + 1;
+  static constexpr int kTPSet = sizeof(T) == 8 ? DGP_RELAXW_TP_F64 : DGP_RELAXW_TP_F32;
+  static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
+  static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
+  static constexpr int kMinBlocks = sizeof(T) == 8 ? DGP_RELAXW_MINB_F64 : DGP_RELAXW_MINB_F32;
+  static constexpr bool kUse = (sizeof(T) == 8 ? DGP_RELAXW_WAVE_F64 : DGP_RELAXW_WAVE_F32) && (kT <= 64) &&
+                               (64 % kT == 0);
   static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
   static constexpr int kTile = H * kSP;
   static constexpr bool kWave = (kT <= 64) && (64 % kT == 0);
@@ -294,7 +318,7 @@ __device__ __forceinline__ int wave_sum(int x) {
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__((RelaxWGeo<T, N>::kThreads))
+__global__ void __launch_bounds__((RelaxWGeo<T, N>::kThreads), (RelaxWGeo<T, N>::kMinBlocks))
 k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
           cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
           const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
@@ -304,7 +328,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   constexpr int R = W::R, TP = W::kTP, TT = W::kT, NT = W::kThreads, H = N / 2 + 1, SP = W::kSP;
   constexpr int NPF = W::kNPF;
   constexpr size_t N3 = (size_t)N * N * N, NN = (size_t)N * N;
-  constexpr bool kPreload = sizeof(T) == 4;   // u and S fetched during the last transform (float only)
+  constexpr bool kPreload = DGP_RELAXW_PRELOAD && sizeof(T) == 4;   // u and S fetched during the last transform
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
@@ -313,6 +337,8 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   const int i2 = tile * 2 * TP;
   const int c = threadIdx.x / TT, t = threadIdx.x % TT;   // transform mapping
   __shared__ cx<T> lds[2 * W::kTile];
+  // optional separate exchange region, one padded row per transform
+  __shared__ cx<T> xbuf[DGP_RELAXW_XBUF ? TP * (N + N / 16) : 1];
   __shared__ double redd[W::kWaves];
   __shared__ int redi[W::kWaves];
 
@@ -378,8 +404,13 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
         spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
       }
     }
-    LdsPair<T, SP, W::kWave> X{buf, c};
-    fft<T, N, P, +1>(v, tw, X, t);
+    if constexpr (DGP_RELAXW_XBUF) {
+      LdsRow<T, N, W::kWave> X{xbuf, c};
+      fft<T, N, P, +1>(v, tw, X, t);
+    } else {
+      LdsPair<T, SP, W::kWave> X{buf, c};
+      fft<T, N, P, +1>(v, tw, X, t);
+    }
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -445,8 +476,13 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   }
   // forward axis-0 transform of u^(n+1), exchanges in the transform's own columns of tile 1
   {
-    LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
-    fft<T, N, P, -1>(v, tw, X, t);
+    if constexpr (DGP_RELAXW_XBUF) {
+      LdsRow<T, N, W::kWave> X{xbuf, c};
+      fft<T, N, P, -1>(v, tw, X, t);
+    } else {
+      LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
+      fft<T, N, P, -1>(v, tw, X, t);
+    }
   }
   abs_r = wave_sum<W::kWidth>(abs_r);
   nbad = wave_sum<W::kWidth>(nbad);
@@ -527,6 +563,7 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
         C.status = 0;
         C.result = C.cur;
         C.resid = r;
+        C.final_bad = nbad;   // that pass's update sits in buffer C.out
         done = true;
       } else if (r < C.resid_min) {
         C.resid_min = r;
@@ -621,13 +658,14 @@ template <typename T, int N>
 static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
                     const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
   using G = typename RelaxGeo<T, N>::G;
+  using W = RelaxWGeo<T, N>;
   constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
-  dim3 grid(N / (2 * G::kTP), N, batch);
-  if constexpr ((sizeof(T) == 8 ? DGP_RELAX_WAVE_F64 : DGP_RELAX_WAVE_F32) && RelaxWGeo<T, N>::kWave) {
-    static_assert(RelaxWGeo<T, N>::kTP == G::kTP, "tile geometry shared with relax_groups");
-    hipLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield,
+  if constexpr (W::kUse) {
+    dim3 grid(N / (2 * W::kTP), N, batch);
+    hipLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(W::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield,
                        spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
   } else {
+    dim3 grid(N / (2 * G::kTP), N, batch);
     hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
                        partial, mean_u, cfg, ctl, twiddles<T>(N));
   }
@@ -648,11 +686,17 @@ void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* sp
   }
 }
 
+// column pairs per workgroup of the relaxation kernel that launches for (T, N)
+template <typename T, int N>
+static constexpr int relax_tp() {
+  return RelaxWGeo<T, N>::kUse ? RelaxWGeo<T, N>::kTP : RelaxGeo<T, N>::G::kTP;
+}
+
 int relax_groups(int n, int elem_bytes) {
   int tp = 0;
 #define C(NN)                                                                       \
   case NN:                                                                          \
-    tp = (elem_bytes == 8) ? RelaxGeo<double, NN>::G::kTP : RelaxGeo<float, NN>::G::kTP; \
+    tp = (elem_bytes == 8) ? relax_tp<double, NN>() : relax_tp<float, NN>();       \
     break;
   switch (n) { C(8) C(16) C(32) C(64) C(128) C(256) C(512) default: return 0; }
 #undef C
@@ -678,6 +722,7 @@ __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict_
   C.bad_seen = 0;
   C.passes = 0;
   C.last_bad = 0;
+  C.final_bad = -1;
   C.eps = eps[b];
   C.resid = 0.0;
   C.resid_min = __builtin_huge_val();

@@ -46,8 +46,13 @@ def lognormal_delta(n, box, sigma, seed, slope=-2.0):
     return np.exp(g - 0.5 * sigma * sigma) - 1.0
 
 
-def zeldovich_load(n_side, box, seed, slope=-1.5, kc=1.0, rms_disp=2.0, dtype=np.float64):
-    """Zel'dovich particle load: (positions (3, Np) of ``dtype``, displacement (3, Np) float64)."""
+def zeldovich_load(n_side, box, seed, slope=-1.5, kc=1.0, rms_disp=2.0, dtype=np.float64, block=0):
+    """Zel'dovich particle load: (positions (3, Np) of ``dtype``, displacement (3, Np) float64).
+
+    Particles are stored in lattice order (axis 2 fastest); with ``block`` = b > 0 they are
+    stored in Lagrangian blocks of b^3 lattice sites instead (blocks in lattice order, sites
+    in lattice order inside a block), a spatially coherent order.
+    """
     n = n_side
     dl = gaussian_field(n, box, seed, slope, kc)
     dk = np.fft.rfftn(dl)
@@ -70,6 +75,12 @@ def zeldovich_load(n_side, box, seed, slope=-1.5, kc=1.0, rms_disp=2.0, dtype=np
     x = x - box * np.floor(x / box)
     x = x.astype(dtype)
     x = np.where(x >= dtype(box), x - dtype(box), x).astype(dtype)
+    if block:
+        if n % block:
+            raise ValueError("block must divide n_side")
+        m = n // block
+        order = np.arange(n ** 3).reshape(m, block, m, block, m, block).transpose(0, 2, 4, 1, 3, 5).ravel()
+        x, psi = x[:, order], psi[:, order]
     return np.ascontiguousarray(x), np.ascontiguousarray(psi)
 
 

@@ -178,6 +178,32 @@ def test_deposit_bit_exact(dgp, fp32):
         assert torch.equal(g, g2)
 
 
+def _deposit_cases():
+    n, box = 32, 64.0
+    rng = np.random.default_rng(5)
+    blocked, _ = inputs.zeldovich_load(n, box, 13, block=8)
+    shifted = (blocked + 0.49 * box) % box                      # blocks straddle the periodic faces
+    uniform = rng.uniform(0.0, box, (3, 5003))                   # boxes exceed the LDS bins: direct path
+    cluster = (rng.uniform(-0.7, 0.7, (3, 700)) + box) % box     # one chunk wrapping the corner cell
+    mixed = np.concatenate([cluster, uniform[:, :333]], axis=1)  # ragged tail chunk
+    tiny = rng.uniform(0.0, box, (3, 37))
+    return n, box, {"blocked": blocked, "shifted": shifted, "uniform": uniform, "mixed": mixed, "tiny": tiny}
+
+
+@pytest.mark.parametrize("case", ["blocked", "shifted", "uniform", "mixed", "tiny"])
+def test_deposit_binned_bit_exact(dgp, case):
+    """The LDS-binned deposit (compact chunks) and its direct fallback (spread chunks)
+    both reproduce the oracle's integer mesh exactly."""
+    say("deposit binned", case)
+    n, box, cases = _deposit_cases()
+    pos = np.ascontiguousarray(cases[case])
+    grid_ref, _ = pm.deposit(pos, n, box)
+    with dgp.Plan(n, box) as plan:
+        g = torch.zeros(n ** 3, dtype=torch.int64, device="cuda")
+        plan.deposit(to_dev(pos, torch.float64), g, None)
+        assert np.array_equal(g.cpu().numpy().reshape(n, n, n), grid_ref)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_pm_forces(dgp, mode):
     say("forces", mode)
@@ -224,6 +250,31 @@ def test_step_matches_oracle(dgp, fp32):
         tol_x = 1e-10 if not fp32 else 2e-5
         assert rel_l2(dx, dx_ref) <= tol_x
         assert rel_l2(tv.cpu().numpy(), v_ref) <= (1e-12 if not fp32 else 1e-7)
+
+
+@pytest.mark.parametrize("case", ["blocked", "shifted", "uniform"])
+def test_step_particle_orders(dgp, case):
+    """Kick-drift with the chunk's force mesh staged in LDS (compact chunks) and the direct
+    gather (spread chunks, uniform positions) against the oracle step."""
+    say("step order", case)
+    n, box, cases = _deposit_cases()
+    a, dlna = 0.5, 0.005
+    pos = np.ascontiguousarray(cases[case])
+    vel = np.random.default_rng(8).normal(0.0, 0.3, pos.shape)
+    mode = 0 if case != "uniform" else 2          # uniform positions: GR forces (no field solve)
+    _, delta = pm.deposit(pos, n, box)
+    lam = calibrate_lambda(delta, box, 1.78)
+    op = oracle_params(lam=lam, tol=1e-11)
+    x_ref, v_ref, _, _ = pm.step(pos, vel, None, a, dlna, box, n, op, OM0, mode=mode)
+    with dgp.Plan(n, box) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, _ = plan.step(gpu_params(dgp, lam=lam, tol=1e-11, force_mode=mode), tp, tv, u, dlna)
+        assert st == 0
+        dx = (tp.cpu().numpy() - pos + box / 2) % box - box / 2
+        dx_ref = (x_ref - pos + box / 2) % box - box / 2
+        assert rel_l2(dx, dx_ref) <= 1e-10
+        assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= 1e-10
 
 
 def test_step_bad_point_regime_same_decisions(dgp):
