@@ -182,7 +182,7 @@ struct dgp_plan {
   double* U = nullptr;               // [3][B][n3]
   double* S = nullptr;               // [B][n3]
   cx<double>* spec_u = nullptr;      // [B][hs]
-  cx<double>* spec6 = nullptr;       // [6][B][hs]
+  cx<double>* spec6 = nullptr;       // [8][B][hs]; fields 6, 7: axis-0/1 spectra of delta (kept) and u
   double* partial = nullptr;         // [B][groups][2]
   int groups64 = 0;
   // float32 solve workspace (precision form)
@@ -198,6 +198,8 @@ struct dgp_plan {
   int* n_active = nullptr;
   int* n_active_host = nullptr;
   double* mean_u = nullptr;          // [B]
+  double* means_host = nullptr;      // pinned [B]: <u> of the returned iterates
+  int hint32 = 0, hint64 = 0;        // passes of the last solve (float32 phase, float64 solve or phase)
   double* vec = nullptr;             // [4][B] scratch scalars (eps, means)
   double* red = nullptr;             // reduction scratch
   // PM (batch 1)
@@ -322,7 +324,7 @@ static int plan_alloc(dgp_plan* pl) {
   TRY(dalloc(pl, &pl->U, 3 * B * n3));
   TRY(dalloc(pl, &pl->S, B * n3));
   TRY(dalloc(pl, &pl->spec_u, B * hs));
-  TRY(dalloc(pl, &pl->spec6, 6 * B * hs));
+  TRY(dalloc(pl, &pl->spec6, 8 * B * hs));   // 6 pass spectra + the delta and u spectra of the PM step
   pl->groups64 = relax_groups(pl->n, 8);
   TRY(dalloc(pl, &pl->partial, B * pl->groups64 * 2));
   if (pl->precision == DGP_FP32) {
@@ -338,6 +340,7 @@ static int plan_alloc(dgp_plan* pl) {
   TRY(dalloc(pl, &pl->n_active, 1));
   TRY(halloc(pl, &pl->n_active_host, 1));
   TRY(dalloc(pl, &pl->mean_u, B));
+  TRY(halloc(pl, &pl->means_host, B));
   TRY(dalloc(pl, &pl->vec, 4 * B));
   TRY(dalloc(pl, &pl->red, absmean_scratch_doubles(n3, (int)B) + 16));
   if (B == 1) {
@@ -450,19 +453,20 @@ struct Ws {
 static Ws<double> ws64(dgp_plan* pl) { return {pl->U, pl->S, pl->spec_u, pl->spec6, pl->partial, pl->groups64}; }
 static Ws<float> ws32(dgp_plan* pl) { return {pl->U32, pl->S32, pl->spec_u32, pl->spec6_32, pl->partial32, pl->groups32}; }
 
-// S and the linear guess from delta (float64 source spectrum, written in precision T).
-template <typename T>
-static int setup_source(dgp_plan* pl, const dgp_params* p, const T* delta_t, Ws<T>& w, bool want_linear,
+// S and the linear guess from delta (float64).  The axis-0/1 spectrum of delta stays in
+// spectral field 6, where the PM step's force computation picks it up.
+static int setup_source(dgp_plan* pl, const dgp_params* p, const double* delta, Ws<double>& w, bool want_linear,
                         hipStream_t s) {
   const int n = pl->n, B = pl->batch;
   const size_t fs = (size_t)B * pl->hs;
   const SpecCoef cf = spec_coef(pl, p);
-  Timed tm(pl, s, tcls<T>(DGP_T_SETUP));
-  TRY(fwd3<T>(pl, delta_t, w.spec_u, B, nullptr, s));
-  launch_p3<T>(n, SPEC_SOURCE, w.spec_u, fs, 1, w.spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
-  launch_p2<T>(n, w.spec6, 2, B, +1, nullptr, s);
-  launch_p1_inv<T>(n, w.spec6, w.S, B, nullptr, s);
-  if (want_linear) launch_p1_inv<T>(n, w.spec6 + fs, w.U, B, nullptr, s);
+  Timed tm(pl, s, DGP_T_SETUP);
+  cx<double>* dspec = w.spec6 + 6 * fs;
+  TRY(fwd3<double>(pl, delta, dspec, B, nullptr, s));
+  launch_p3<double>(n, SPEC_SOURCE, dspec, fs, 1, w.spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
+  launch_p2<double>(n, w.spec6, 2, B, +1, nullptr, s);
+  launch_p1_inv<double>(n, w.spec6, w.S, B, nullptr, s);
+  if (want_linear) launch_p1_inv<double>(n, w.spec6 + fs, w.U, B, nullptr, s);
   LAUNCHCHK();
   return DGP_OK;
 }
@@ -500,15 +504,19 @@ static int enqueue_pass(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const Solve
 // Run passes until every batch element is done.  The host reads the control
 // blocks between chunks and sizes the next chunk from the observed linear
 // convergence rate, so few passes are launched after the last element has
-// stopped (such launches exit at once but still cost a launch).
+// stopped (such launches exit at once but still cost a launch).  `first` sets
+// the first chunk (0: two passes); with check = false the first chunk is only
+// enqueued (no host round trip) and the loop returns.
 template <typename T>
-static int run_loop(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg& cfg, hipStream_t s, int* passes) {
+static int run_loop(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg& cfg, hipStream_t s, int first,
+                    bool check) {
   const int B = pl->batch;
   const int cap = p->check_every > 0 ? p->check_every : 4;
   int k = 0;
-  int chunk = std::min(2, cfg.max_iter + 1);
+  int chunk = std::min(first > 0 ? first : 2, cfg.max_iter + 1);
   for (;;) {
     for (int i = 0; i < chunk && k <= cfg.max_iter; ++i, ++k) TRY(enqueue_pass<T>(pl, p, w, cfg, s));
+    if (!check) return DGP_OK;
     HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     timing_flush(pl);
@@ -531,48 +539,49 @@ static int run_loop(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg&
     if (active == 0 || k > cfg.max_iter) break;
     chunk = next;
   }
-  *passes = k;
   return DGP_OK;
+}
+
+// passes the slowest element needed (control blocks already on the host)
+static int max_passes(const dgp_plan* pl) {
+  int m = 0;
+  for (int b = 0; b < pl->batch; ++b) m = std::max(m, pl->ctl_host[b].passes);
+  return m;
 }
 
 static int status_rank(int st) { return st == DGP_OK ? 0 : (st == DGP_NOT_CONVERGED ? 2 : 1); }
 
-// Copy the decided iterates into u_state and fill info; returns the worst status.
+// Enqueue the copy of the decided iterates into u_state (the device picks each
+// element's buffer), their means, and the copies of the control blocks and means to
+// pinned host memory.  collect_finish reads them once the stream has been synchronised.
 template <typename T>
-static int collect(dgp_plan* pl, Ws<T>& w, double* u_state, dgp_info* info, int passes_fp64, hipStream_t s) {
+static int collect_enqueue(dgp_plan* pl, Ws<T>& w, double* u_state, hipStream_t s) {
   const int B = pl->batch;
+  launch_take_result<T>(pl->ctl, w.U, B, pl->n3, u_state, s);
+  launch_absmean<double>(pl->n3, u_state, B, pl->red, pl->vec, pl->vec + B, s);
+  HIPCHK(hipMemcpyAsync(pl->means_host, pl->vec + B, sizeof(double) * B, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  int worst = DGP_OK;
-  for (int b = 0; b < B; ++b) {
-    const SolveCtl& C = pl->ctl_host[b];
-    const T* src = w.U + ((size_t)C.result * B + b) * pl->n3;
-    if constexpr (sizeof(T) == 8) {
-      HIPCHK(hipMemcpyAsync(u_state + (size_t)b * pl->n3, src, sizeof(double) * pl->n3, hipMemcpyDeviceToDevice, s));
-    } else {
-      launch_convert<double>(pl->n3, src, 1, u_state + (size_t)b * pl->n3, s);
-    }
-    const int st = C.status;
-    if (status_rank(st) > status_rank(worst)) worst = st;
-  }
   LAUNCHCHK();
-  if (info) {
-    launch_absmean<double>(pl->n3, u_state, B, pl->red, pl->vec, pl->vec + B, s);
-    std::vector<double> means(B);
-    HIPCHK(hipMemcpyAsync(means.data(), pl->vec + B, sizeof(double) * B, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (int b = 0; b < B; ++b) {
-      const SolveCtl& C = pl->ctl_host[b];
-      info[b].status = C.status;
-      info[b].iters = C.iters;
-      info[b].passes = C.passes;
-      info[b].passes_fp64 = passes_fp64 >= 0 ? passes_fp64 : C.passes;
-      info[b].resid = C.resid;
-      info[b].resid_min = C.resid_min;
-      info[b].eps = C.eps;
-      info[b].bad_fraction = C.bad_frac;
-      info[b].mean_u = means[b];
-    }
+  return DGP_OK;
+}
+
+// After the stream is synchronised: fill info and return the worst status.
+static int collect_finish(dgp_plan* pl, dgp_info* info, float ms) {
+  int worst = DGP_OK;
+  for (int b = 0; b < pl->batch; ++b) {
+    const SolveCtl& C = pl->ctl_host[b];
+    if (status_rank(C.status) > status_rank(worst)) worst = C.status;
+    if (!info) continue;
+    info[b].status = C.status;
+    info[b].iters = C.iters1 + C.iters;
+    info[b].passes = C.passes1 + C.passes;
+    info[b].passes_fp64 = C.passes;
+    info[b].resid = C.resid;
+    info[b].resid_min = C.resid_min;
+    info[b].eps = C.eps;
+    info[b].bad_fraction = C.bad_frac;
+    info[b].mean_u = pl->means_host[b];
+    info[b].ms_total = ms;
   }
   return worst;
 }
@@ -591,11 +600,10 @@ static int c_field(dgp_plan* pl, const dgp_params* p, const double* u, double* c
 }
 
 // plain float64 solve from the chosen initial iterate
-static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
-                   hipStream_t s) {
+static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s) {
   Ws<double> w = ws64(pl);
   const int B = pl->batch;
-  TRY(setup_source<double>(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
+  TRY(setup_source(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
   if (p->init == DGP_INIT_WARM) {
     HIPCHK(hipMemcpyAsync(w.U, u_state, sizeof(double) * B * pl->n3, hipMemcpyDeviceToDevice, s));
   } else if (p->init == DGP_INIT_ZERO) {
@@ -606,13 +614,17 @@ static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
   // a pass starts from the axis-0 spectrum of its iterate (what the fused pass writes)
   launch_p1_fwd<double>(pl->n, w.U, w.spec_u, B, nullptr, s);
   const SolveCfg cfg = solve_cfg(pl, p, p->tol, p->max_iter);
-  int passes = 0;
-  TRY(run_loop<double>(pl, p, w, cfg, s, &passes));
-  return collect<double>(pl, w, u_state, info, -1, s);
+  TRY(run_loop<double>(pl, p, w, cfg, s, pl->hint64, true));
+  pl->hint64 = max_passes(pl);
+  return collect_enqueue<double>(pl, w, u_state, s);
 }
 
-int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
-                   hipStream_t s);
+int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s);
+
+// Enqueue a solve in the plan's form; ends with collect_enqueue (no final synchronisation).
+static int solve_enqueue(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s) {
+  return pl->precision == DGP_FP32 ? solve32_polish(pl, p, delta, u_state, s) : solve64(pl, p, delta, u_state, s);
+}
 
 extern "C" int dgp_solve_field(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, double* c_out,
                                dgp_info* info, void* stream) {
@@ -621,46 +633,35 @@ extern "C" int dgp_solve_field(dgp_plan* pl, const dgp_params* p, const double* 
   if (!delta || !u_state) return fail(DGP_E_INVALID, "delta and u_state are required");
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipEventRecord(pl->ev0, s));
-  int st;
-  if (pl->precision == DGP_FP32)
-    st = solve32_polish(pl, p, delta, u_state, info, s);
-  else
-    st = solve64(pl, p, delta, u_state, info, s);
-  if (st < 0) return st;
+  TRY(solve_enqueue(pl, p, delta, u_state, s));
   if (c_out) TRY(c_field(pl, p, u_state, c_out, s));
   HIPCHK(hipEventRecord(pl->ev1, s));
   HIPCHK(hipEventSynchronize(pl->ev1));
   timing_flush(pl);
-  if (info) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
-    for (int b = 0; b < pl->batch; ++b) info[b].ms_total = ms;
-  }
-  return st;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+  return collect_finish(pl, info, ms);
 }
 
 // ------------------------------------------------------------------ precision form: float32 passes + float64 polish
 #ifndef DGP_SWITCH_TOL
 #define DGP_SWITCH_TOL 1e-6
 #endif
-#ifndef DGP_SWITCH_HANDOFF
-#define DGP_SWITCH_HANDOFF 1
-#endif
+
 // Phase 1 runs float32 relaxation passes (float64 pointwise arithmetic and
 // reductions) from the initial guess until the float32 residual reaches
 // max(tol, switch_tol) (or phase 1 ends on max_iter or bad points); phase 2
 // continues with float64 passes, from the update that the last float32 pass
 // computed, until the float64 residual meets tol.  The returned residual is always
 // a float64 evaluation.
-int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, dgp_info* info,
-                   hipStream_t s) {
+int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s) {
   const int B = pl->batch;
   const size_t n3 = pl->n3;
   Ws<float> w32 = ws32(pl);
   Ws<double> w = ws64(pl);
   // the source (and the linear guess) are formed once in float64: phase 2 needs them
   // exact, and phase 1 takes their rounding, which is closer than a float32 evaluation
-  TRY(setup_source<double>(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
+  TRY(setup_source(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
   launch_convert<float>(B * n3, w.S, 0, w32.S, s);
   if (p->init == DGP_INIT_LINEAR) {
     launch_convert<float>(B * n3, w.U, 0, w32.U, s);
@@ -669,44 +670,33 @@ int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
   } else {
     HIPCHK(hipMemsetAsync(w32.U, 0, sizeof(float) * B * n3, s));
   }
-  // eps = <|S|> of the float64 source; it stays in pl->vec for both phases
+  // eps = <|S|> of the float64 source; it stays in the control blocks for both phases
   launch_absmean<double>(n3, w.S, B, pl->red, pl->vec, nullptr, s);
   launch_ctl_init(pl->ctl, pl->vec, B, s);
   launch_p1_fwd<float>(pl->n, w32.U, w32.spec_u, B, nullptr, s);
   const double switch_tol = std::max(p->tol, double(DGP_SWITCH_TOL));
-  SolveCfg cfg32 = solve_cfg(pl, p, switch_tol, p->max_iter);
-  int passes32 = 0;
-  TRY(run_loop<float>(pl, p, w32, cfg32, s, &passes32));
-  // float32 result -> float64 warm start
-  HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::vector<int> p32(B), it32(B);
-  for (int b = 0; b < B; ++b) {
-    const SolveCtl& C = pl->ctl_host[b];
-    // warm start: the update computed by the pass that met the switch tolerance (one
-    // relaxation step past the checked iterate) unless that update met bad points
-    const int src = (DGP_SWITCH_HANDOFF && C.status == 0 && C.final_bad == 0) ? C.out : C.result;
-    launch_convert<double>(n3, w32.U + ((size_t)src * B + b) * n3, 1, pl->U + (size_t)b * n3, s);
-    p32[b] = C.passes;
-    it32[b] = C.iters + (src == C.out ? 1 : 0);
-  }
-  LAUNCHCHK();
-  launch_ctl_init(pl->ctl, pl->vec, B, s);
+  const SolveCfg cfg32 = solve_cfg(pl, p, switch_tol, p->max_iter);
+  // phase 1: after the plan's first solve, one pass more than the last solve's phase 1
+  // took, enqueued without a host round trip (passes after an element stops exit at once;
+  // an element still running at the end continues in phase 2)
+  if (pl->hint32 > 0)
+    TRY(run_loop<float>(pl, p, w32, cfg32, s, pl->hint32 + 1, false));
+  else
+    TRY(run_loop<float>(pl, p, w32, cfg32, s, 0, true));
+  launch_handoff(pl->ctl, w32.U, B, n3, w.U, s);
   launch_p1_fwd<double>(pl->n, w.U, w.spec_u, B, nullptr, s);
-  const int left = std::max(0, p->max_iter - *std::min_element(it32.begin(), it32.end()));
-  SolveCfg cfg = solve_cfg(pl, p, p->tol, left);
-  int passes = 0;
-  TRY(run_loop<double>(pl, p, w, cfg, s, &passes));
-  const int st = collect<double>(pl, w, u_state, info, -1, s);
-  if (st < 0) return st;
-  if (info) {
-    for (int b = 0; b < B; ++b) {
-      info[b].passes_fp64 = info[b].passes;
-      info[b].passes += p32[b];
-      info[b].iters += it32[b];
-    }
+  const SolveCfg cfg = solve_cfg(pl, p, p->tol, p->max_iter);
+  TRY(run_loop<double>(pl, p, w, cfg, s, pl->hint64, true));
+  // learn the pass counts for the next solve on this plan
+  int p1 = 0;
+  bool cut = false;
+  for (int b = 0; b < B; ++b) {
+    p1 = std::max(p1, pl->ctl_host[b].passes1);
+    cut = cut || !pl->ctl_host[b].phase1_done;
   }
-  return st;
+  pl->hint32 = cut ? p1 + 2 : p1;
+  pl->hint64 = max_passes(pl);
+  return collect_enqueue<double>(pl, w, u_state, s);
 }
 
 // ------------------------------------------------------------------ PM
@@ -741,24 +731,30 @@ extern "C" int dgp_deposit(dgp_plan* pl, const void* pos, int pos_is_fp32, long 
   return DGP_OK;
 }
 
-// force mesh g = -(c/H0)^2 grad phi, [3][n3] into mesh3 (and phi into phi_n when given)
+// force mesh g = -(c/H0)^2 grad phi, [3][n3] into mesh3 (and phi into phi_n when given).
+// delta_ready: spectral field 6 already holds the axis-0/1 spectrum of delta (left there by
+// the solve's setup on the same delta).
 static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u, double* mesh3,
-                      double* phi_n, hipStream_t s) {
+                      double* phi_n, bool delta_ready, hipStream_t s) {
   Timed tm(pl, s, DGP_T_FORCES);
   const int n = pl->n;
   const size_t fs = pl->hs;
   SpecCoef cf = spec_coef(pl, p);
   cf.with_phi = phi_n ? 1 : 0;
   const bool use_u = p->force_mode == DGP_FORCE_NLDGP;
-  launch_p1_fwd<double>(n, delta, pl->spec6, 1, nullptr, s);
-  if (use_u) launch_p1_fwd<double>(n, u, pl->spec6 + fs, 1, nullptr, s);
-  launch_p2<double>(n, pl->spec6, use_u ? 2 : 1, 1, -1, nullptr, s);
+  cx<double>* fin = pl->spec6 + 6 * fs;   // delta, then u
+  if (!delta_ready) launch_p1_fwd<double>(n, delta, fin, 1, nullptr, s);
+  if (use_u) launch_p1_fwd<double>(n, u, fin + fs, 1, nullptr, s);
+  if (!delta_ready)
+    launch_p2<double>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
+  else if (use_u)
+    launch_p2<double>(n, fin + fs, 1, 1, -1, nullptr, s);
   const int nout = phi_n ? 4 : 3;
-  launch_p3<double>(n, SPEC_FORCES, pl->spec6, fs, use_u ? 2 : 1, pl->spec6 + 2 * fs, fs, nout, 1, cf, nullptr,
-                    nullptr, nullptr, nullptr, s);
-  launch_p2<double>(n, pl->spec6 + 2 * fs, nout, 1, +1, nullptr, s);
-  for (int d = 0; d < 3; ++d) launch_p1_inv<double>(n, pl->spec6 + (2 + d) * fs, mesh3 + d * pl->n3, 1, nullptr, s);
-  if (phi_n) launch_p1_inv<double>(n, pl->spec6 + 5 * fs, phi_n, 1, nullptr, s);
+  launch_p3<double>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6, fs, nout, 1, cf, nullptr, nullptr, nullptr,
+                    nullptr, s);
+  launch_p2<double>(n, pl->spec6, nout, 1, +1, nullptr, s);
+  launch_p1_inv<double>(n, pl->spec6, mesh3, 3, nullptr, s);
+  if (phi_n) launch_p1_inv<double>(n, pl->spec6 + 3 * fs, phi_n, 1, nullptr, s);
   LAUNCHCHK();
   return DGP_OK;
 }
@@ -772,7 +768,7 @@ extern "C" int dgp_pm_forces(dgp_plan* pl, const dgp_params* p, const double* de
   if (!delta || !pos || !force || np < 1) return fail(DGP_E_INVALID, "delta, pos, force and np >= 1 are required");
   if (p->force_mode == DGP_FORCE_NLDGP && !u_state) return fail(DGP_E_INVALID, "u_state is required for nlDGP forces");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  TRY(force_mesh(pl, p, delta, u_state, pl->mesh3, phi_n, s));
+  TRY(force_mesh(pl, p, delta, u_state, pl->mesh3, phi_n, false, s));
   launch_interp(pl->n, pl->box, pl->mesh3, pos, pos_is_fp32, np, force, s);
   LAUNCHCHK();
   return DGP_OK;
@@ -787,12 +783,13 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
   if (!std::isfinite(dlna)) return fail(DGP_E_INVALID, "dlna must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
   TRY(deposit_impl(pl, pos, is_fp32, np, pl->grid, pl->delta, false, s));
-  int st = DGP_OK;
-  if (p->force_mode == DGP_FORCE_NLDGP) {
-    st = dgp_solve_field(pl, p, pl->delta, u_state, nullptr, info, stream);
-    if (st < 0) return st;
+  const bool solve = p->force_mode == DGP_FORCE_NLDGP;
+  if (solve) {
+    HIPCHK(hipEventRecord(pl->ev0, s));
+    TRY(solve_enqueue(pl, p, pl->delta, u_state, s));
+    HIPCHK(hipEventRecord(pl->ev1, s));
   }
-  TRY(force_mesh(pl, p, pl->delta, u_state, pl->mesh3, nullptr, s));
+  TRY(force_mesh(pl, p, pl->delta, u_state, pl->mesh3, nullptr, solve, s));
   const double a = p->a;
   const double e_n = hubble_E(p->omega_m0, a);
   const double a_h = a * std::exp(0.5 * dlna);
@@ -806,7 +803,10 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));
   timing_flush(pl);
-  return st;
+  if (!solve) return DGP_OK;
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
+  return collect_finish(pl, info, ms);
 }
 
 extern "C" int dgp_deposit_backward(dgp_plan* pl, const void* pos, int pos_is_fp32, long long np,

@@ -57,6 +57,9 @@ struct SolveCtl {
   int passes;       // residual evaluations executed
   int last_bad;     // bad points of the last update
   int final_bad;    // bad points of the update computed by the pass that met tol (-1: none)
+  int iters1;       // precision form: updates and passes of the float32 phase (0 otherwise)
+  int passes1;
+  int phase1_done;  // the float32 phase had decided before the float64 phase started
   double eps;       // <|S|>
   double resid;     // r of the returned iterate
   double resid_min;
@@ -107,6 +110,13 @@ struct RowTile {
 // that one XCD works through a contiguous range of them, so neighbouring tiles that share
 // 128-byte lines are fetched through the same L2.  The map is a bijection of the grid, so the
 // result does not depend on how the hardware actually dispatches.
+// 1D form for particle chunks: consecutive chunks (neighbouring Lagrangian blocks, whose
+// mesh boxes overlap) run on the same XCD and share its L2.
+__device__ __forceinline__ long long xcd_chunk() {
+  const long long g = gridDim.x, i = blockIdx.x;
+  return ((g & 7) == 0) ? (i & 7) * (g >> 3) + (i >> 3) : i;
+}
+
 __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
   const int gx = gridDim.x, g = gridDim.x * gridDim.y;
   const int i = blockIdx.y * gx + blockIdx.x;
@@ -149,6 +159,14 @@ void launch_absmean(size_t n3, const T* x, int batch, double* scratch, double* a
 size_t absmean_scratch_doubles(size_t n3, int batch);
 // control blocks: eps from abs_mean[b], buffer roles reset
 void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s);
+// end of the float32 phase: per element, the warm start for float64 (the update of the
+// pass that met the switch tolerance unless it met bad points, else the checked iterate;
+// the latest iterate if the phase was still running) converted into dst[B][n3], then the
+// control re-initialised for the float64 phase with the float32 counts kept
+void launch_handoff(SolveCtl* ctl, const float* U32, int batch, size_t n3, double* dst, hipStream_t s);
+// the returned iterate of every element, as float64, into dst[B][n3]
+template <typename T>
+void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, hipStream_t s);
 
 // per-batch means of the two columns of [batch][groups][2] partial sums
 void launch_pair_means(const double* part, int groups, size_t n3, int batch, double* out0, double* out1,

@@ -18,13 +18,13 @@ struct Cic {
   double w0[3], w1[3];
 };
 
-template <typename P>
-__device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, long long p, int n, double scale) {
+// cell and weights of a particle at x (already in mesh units: x = pos * N / L)
+__device__ __forceinline__ Cic cic_at(const double (&s3)[3], int n) {
 #pragma clang fp contract(off)
   Cic c;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double s = double(pos[(size_t)d * np + p]) * scale;
+    const double s = s3[d];
     const double fl = floor(s);
     const double f = s - fl;
     long long i = (long long)fl % n;
@@ -35,6 +35,15 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
     c.w1[d] = f;
   }
   return c;
+}
+
+template <typename P>
+__device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, long long p, int n, double scale) {
+#pragma clang fp contract(off)
+  double s3[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s3[d] = double(pos[(size_t)d * np + p]) * scale;
+  return cic_at(s3, n);
 }
 
 template <typename P>
@@ -91,11 +100,13 @@ __device__ __forceinline__ int periodic_offset(int i, int r, int n) {
 
 // Periodic bounding box of a chunk's CIC base cells, relative to the base cell cr of its
 // first particle: offsets in [-n/2, n/2) per axis, box lo[d] .. lo[d] + ext[d] - 1 (the
-// +1 corners included).  Returns true when the box volume is at most `cap`.  Every
-// thread of the (256-thread) workgroup must call it.
+// +1 corners included).  xs holds the positions of the thread's particles (p0 + threadIdx.x
+// + 256 k), loaded by the caller.  Returns true when the box volume is at most `cap`.
+// Every thread of the (256-thread) workgroup must call it.
 template <int PPT, typename P>
-__device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, long long np, int n, double scale, long long p0,
-                                          int cap, Cic& cr, Cic (&cs)[PPT], int (&off)[PPT][3], int (&bx)[6]) {
+__device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, const P (&xs)[PPT][3], long long np, int n,
+                                          double scale, long long p0, int cap, Cic& cr, Cic (&cs)[PPT],
+                                          int (&off)[PPT][3], int (&bx)[6]) {
   __shared__ int wlo[4][3], whi[4][3];
   __shared__ int sbox[7];
   cr = cic_of(pos, np, p0, n, scale);
@@ -104,7 +115,8 @@ __device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, long long n
   for (int k = 0; k < PPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
     if (p < np) {
-      cs[k] = cic_of(pos, np, p, n, scale);
+      const double s3[3] = {double(xs[k][0]) * scale, double(xs[k][1]) * scale, double(xs[k][2]) * scale};
+      cs[k] = cic_at(s3, n);
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         off[k][d] = periodic_offset(cs[k].i0[d], cr.i0[d], n);
@@ -149,6 +161,17 @@ __device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, long long n
   return sbox[6] != 0;
 }
 
+// the positions of the thread's particles in a chunk (unused slots past np left at 0)
+template <int PPT, typename P>
+__device__ __forceinline__ void load_chunk(const P* __restrict__ a, long long np, long long p0, P (&xs)[PPT][3]) {
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const long long p = p0 + threadIdx.x + k * 256;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) xs[k][d] = p < np ? a[(size_t)d * np + p] : P(0);
+  }
+}
+
 // mesh index of box cell i (row-major over the box extents), wrapped onto the periodic mesh
 __device__ __forceinline__ size_t box_cell(int i, const Cic& cr, const int (&bx)[6], int n) {
   const int plane = bx[4] * bx[5];
@@ -165,10 +188,12 @@ __global__ void __launch_bounds__(256)
 k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
 #pragma clang fp contract(off)
   __shared__ unsigned long long hist[kBinCap];
-  const long long p0 = (long long)blockIdx.x * kDepChunk;
+  const long long p0 = xcd_chunk() * kDepChunk;
+  P xs[kDepPPT][3];
+  load_chunk<kDepPPT>(pos, np, p0, xs);
   Cic cr, cs[kDepPPT];
   int off[kDepPPT][3], bx[6];
-  const bool binned = chunk_box<kDepPPT>(pos, np, n, scale, p0, kBinCap, cr, cs, off, bx);
+  const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, kBinCap, cr, cs, off, bx);
   const int vol = bx[3] * bx[4] * bx[5];
   if (binned)
     for (int i = threadIdx.x; i < vol; i += 256) hist[i] = 0ull;
@@ -323,10 +348,14 @@ k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P
 #pragma clang fp contract(off)
   __shared__ double fl[3 * kGatherCap];
   const size_t n3 = (size_t)n * n * n;
-  const long long p0 = (long long)blockIdx.x * kGatherChunk;
+  const long long p0 = xcd_chunk() * kGatherChunk;
+  // positions and velocities are loaded together up front and kept in registers
+  P xs[kGatherPPT][3], vs[kGatherPPT][3];
+  load_chunk<kGatherPPT>(pos, np, p0, xs);
+  load_chunk<kGatherPPT>(vel, np, p0, vs);
   Cic cr, cs[kGatherPPT];
   int off[kGatherPPT][3], bx[6];
-  const bool binned = chunk_box<kGatherPPT>(pos, np, n, scale, p0, kGatherCap, cr, cs, off, bx);
+  const bool binned = chunk_box<kGatherPPT>(pos, xs, np, n, scale, p0, kGatherCap, cr, cs, off, bx);
   if (binned) {
     const int vol = bx[3] * bx[4] * bx[5];
     for (int i = threadIdx.x; i < vol; i += 256) {
@@ -356,8 +385,8 @@ k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const size_t i = (size_t)d * np + p;
-      const double v = double(vel[i]) + kick * f[d];
-      double x = double(pos[i]) + drift * v;
+      const double v = double(vs[k][d]) + kick * f[d];
+      double x = double(xs[k][d]) + drift * v;
       x = x - box * floor(x / box);
       P xo = P(x);
       if (xo >= P(box)) xo = xo - P(box);

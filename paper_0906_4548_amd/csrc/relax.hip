@@ -258,17 +258,14 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 #ifndef DGP_RELAXW_TP_F64
 #define DGP_RELAXW_TP_F64 0
 #endif
-#ifndef DGP_RELAXW_MINB_F32
-#define DGP_RELAXW_MINB_F32 1
+#ifndef DGP_RELAXW_MINW_F32
+#define DGP_RELAXW_MINW_F32 1
 #endif
-#ifndef DGP_RELAXW_MINB_F64
-#define DGP_RELAXW_MINB_F64 3
+#ifndef DGP_RELAXW_MINW_F64
+#define DGP_RELAXW_MINW_F64 3
 #endif
 #ifndef DGP_RELAXW_PRELOAD
 #define DGP_RELAXW_PRELOAD 1
-#endif
-#ifndef DGP_RELAXW_XBUF
-#define DGP_RELAXW_XBUF 0
 #endif
 
 template <typename T, int N>
@@ -279,7 +276,7 @@ struct RelaxWGeo {
   static constexpr int kTPSet = sizeof(T) == 8 ? DGP_RELAXW_TP_F64 : DGP_RELAXW_TP_F32;
   static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
   static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
-  static constexpr int kMinBlocks = sizeof(T) == 8 ? DGP_RELAXW_MINB_F64 : DGP_RELAXW_MINB_F32;
+  static constexpr int kMinWaves = sizeof(T) == 8 ? DGP_RELAXW_MINW_F64 : DGP_RELAXW_MINW_F32;
   static constexpr bool kUse = (sizeof(T) == 8 ? DGP_RELAXW_WAVE_F64 : DGP_RELAXW_WAVE_F32) && (kT <= 64) &&
                                (64 % kT == 0);
   static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
@@ -317,8 +314,9 @@ __device__ __forceinline__ int wave_sum(int x) {
   return x;
 }
 
+// (the second launch bound is the minimum number of wavefronts per SIMD to plan registers for)
 template <typename T, int N>
-__global__ void __launch_bounds__((RelaxWGeo<T, N>::kThreads), (RelaxWGeo<T, N>::kMinBlocks))
+__global__ void __launch_bounds__((RelaxWGeo<T, N>::kThreads), (RelaxWGeo<T, N>::kMinWaves))
 k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
           cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
           const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
@@ -337,8 +335,6 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   const int i2 = tile * 2 * TP;
   const int c = threadIdx.x / TT, t = threadIdx.x % TT;   // transform mapping
   __shared__ cx<T> lds[2 * W::kTile];
-  // optional separate exchange region, one padded row per transform
-  __shared__ cx<T> xbuf[DGP_RELAXW_XBUF ? TP * (N + N / 16) : 1];
   __shared__ double redd[W::kWaves];
   __shared__ int redi[W::kWaves];
 
@@ -404,13 +400,8 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
         spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
       }
     }
-    if constexpr (DGP_RELAXW_XBUF) {
-      LdsRow<T, N, W::kWave> X{xbuf, c};
-      fft<T, N, P, +1>(v, tw, X, t);
-    } else {
-      LdsPair<T, SP, W::kWave> X{buf, c};
-      fft<T, N, P, +1>(v, tw, X, t);
-    }
+    LdsPair<T, SP, W::kWave> X{buf, c};
+    fft<T, N, P, +1>(v, tw, X, t);
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -476,13 +467,8 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   }
   // forward axis-0 transform of u^(n+1), exchanges in the transform's own columns of tile 1
   {
-    if constexpr (DGP_RELAXW_XBUF) {
-      LdsRow<T, N, W::kWave> X{xbuf, c};
-      fft<T, N, P, -1>(v, tw, X, t);
-    } else {
-      LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
-      fft<T, N, P, -1>(v, tw, X, t);
-    }
+    LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
+    fft<T, N, P, -1>(v, tw, X, t);
   }
   abs_r = wave_sum<W::kWidth>(abs_r);
   nbad = wave_sum<W::kWidth>(nbad);
@@ -575,7 +561,7 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
         done = true;
       }
       if (r < C.resid_min) C.resid_min = r;
-      if (!done && n >= cfg.max_iter) {
+      if (!done && n + C.iters1 >= cfg.max_iter) {
         C.status = 1;
         C.result = C.best;
         C.resid = C.resid_min;
@@ -708,10 +694,7 @@ void launch_finalize(const double* partial, int groups, SolveCtl* ctl, const Sol
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, groups, ctl, cfg, n_active);
 }
 
-__global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  SolveCtl& C = ctl[b];
+__device__ void ctl_reset(SolveCtl& C) {
   C.done = 0;
   C.status = 0;
   C.iters = 0;
@@ -723,13 +706,70 @@ __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict_
   C.passes = 0;
   C.last_bad = 0;
   C.final_bad = -1;
-  C.eps = eps[b];
   C.resid = 0.0;
   C.resid_min = __builtin_huge_val();
   C.bad_frac = 0.0;
   C.mean_u = 0.0;
   for (int i = 0; i < kMaxHist; ++i) C.hist[i] = -1.0;
 }
+
+__global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  SolveCtl& C = ctl[b];
+  ctl_reset(C);
+  C.eps = eps[b];
+  C.iters1 = 0;
+  C.passes1 = 0;
+  C.phase1_done = 1;
+}
+
+__device__ __forceinline__ int handoff_buffer(const SolveCtl& C) {
+  if (!C.done) return C.cur;
+  return (C.status == 0 && C.final_bad == 0) ? C.out : C.result;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_take_buffer(const SolveCtl* __restrict__ ctl, const T* __restrict__ U, int batch, size_t n3, double* __restrict__ dst,
+              int handoff) {
+  const int b = blockIdx.y;
+  const int src = handoff ? handoff_buffer(ctl[b]) : ctl[b].result;
+  const T* in = U + ((size_t)src * batch + b) * n3;
+  double* out = dst + (size_t)b * n3;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) out[i] = double(in[i]);
+}
+
+// keeps eps (the float64 source's) and records the float32 phase's counts
+__global__ void k_ctl_phase2(SolveCtl* __restrict__ ctl, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  SolveCtl& C = ctl[b];
+  const int src = handoff_buffer(C);
+  C.iters1 = C.iters + ((C.done && src == C.out) ? 1 : 0);
+  C.passes1 = C.passes;
+  C.phase1_done = C.done;
+  ctl_reset(C);
+}
+
+static unsigned copy_groups(size_t n3) {
+  const size_t g = (n3 + 255) / 256;
+  return unsigned(g > 4096 ? 4096 : g);
+}
+
+void launch_handoff(SolveCtl* ctl, const float* U32, int batch, size_t n3, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_take_buffer<float>), dim3(copy_groups(n3), batch), dim3(256), 0, s, ctl, U32, batch, n3, dst,
+                     1);
+  hipLaunchKernelGGL(k_ctl_phase2, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, batch);
+}
+
+template <typename T>
+void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL((k_take_buffer<T>), dim3(copy_groups(n3), batch), dim3(256), 0, s, ctl, U, batch, n3, dst, 0);
+}
+
+template void launch_take_result<double>(const SolveCtl*, const double*, int, size_t, double*, hipStream_t);
+template void launch_take_result<float>(const SolveCtl*, const float*, int, size_t, double*, hipStream_t);
 
 void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_init, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, eps, batch);
