@@ -14,6 +14,7 @@ Other modes:
                           steps plus a plain 512 MiB device copy for calibration)
   --pmc-summary F W       turn the counter CSVs of two such passes (FETCH_SIZE, then
                           WRITE_SIZE) into the traffic summary kept under profiles/
+  --trace-summary T       per-kernel duration table of a rocprofv3 kernel trace
 
 The solve runs in the precision form (float32 FFTs and pointwise storage,
 float64 residual / discriminant / root / reductions, float64 polish); the plain
@@ -44,6 +45,7 @@ RNL = 1.78          # nonlinear ratio lambda max|u_lin| / alpha (screened; see D
 DLNA = 0.005
 PEAK_HBM = 8.0e12   # bytes/s, MI355X
 BLOCK = 8           # particles stored in Lagrangian blocks of BLOCK^3
+BREAKDOWN_STEPS = 3
 COPY_BYTES = 512 * 1024 * 1024   # calibration copy of the probe: reads and writes this many bytes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_pm_step_256.md")
 # timing class of the library -> device kernel names (prefixes) it launches
@@ -150,6 +152,27 @@ def pmc_summary(fetch_csv, write_csv):
     return "\n".join(lines)
 
 
+def trace_summary(trace_csv, stats_csv=None):
+    """Markdown table of per-kernel durations from a rocprofv3 kernel trace; besides the
+    statistics over every dispatch it gives the average over working dispatches (those
+    above 5 % of the kernel's longest: relaxation launches after convergence exit at once)."""
+    durs = {}
+    with open(trace_csv, newline="") as fh:
+        for row in csv.DictReader(fh):
+            name = kernel_name(row["Kernel_Name"])
+            durs.setdefault(name, []).append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3)
+    total = sum(sum(v) for v in durs.values())
+    lines = ["| kernel | calls | avg us | working | working avg us | min us | max us | total ms | % |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for name, v in sorted(durs.items(), key=lambda kv: -sum(kv[1])):
+        top = max(v)
+        w = [x for x in v if x >= 0.05 * top]
+        lines.append("| `%s` | %d | %.1f | %d | %.1f | %.1f | %.1f | %.2f | %.1f |" % (
+            name, len(v), sum(v) / len(v), len(w), sum(w) / len(w), min(v), top, sum(v) * 1e-3,
+            100.0 * sum(v) / total))
+    return "\n".join(lines)
+
+
 def stored_traffic(cls):
     """Calibrated HBM bytes per dispatch of the kernel behind timing class `cls`, or None when
     no summary exists or the device sources changed since the counters were taken."""
@@ -191,9 +214,14 @@ def main():
     ap.add_argument("--probe", action="store_true", help="short run for hardware-counter passes")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the calibrated traffic summary from two counter passes to stdout")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="write a per-kernel duration table from a rocprofv3 kernel trace to stdout")
     args = ap.parse_args()
     if args.pmc_summary:
         print(pmc_summary(*args.pmc_summary))
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the field solve is built for a single MI355X "
@@ -222,7 +250,8 @@ def main():
         lam = RNL * prm0.alpha / float(ulin.abs().max())
     del delta, ulin
 
-    def run_form(precision, steps, warmup):
+    def run_form(precision, steps, warmup, classes=None):
+        """Run warmup + timed steps; `classes` restricts the event timing (None: every class)."""
         plan = dgp.Plan(N, BOX, precision=precision)
         prm = dgp.params(OM0, A, lam=lam, tol=TOL, max_iter=200, init=dgp.INIT_LINEAR, check_every=8)
         pos = pos0.clone()
@@ -232,6 +261,7 @@ def main():
             plan.step(prm, pos, vel, u, DLNA)
         torch.cuda.synchronize()
         plan.timing(True)
+        plan.timing_classes(classes)
         infos = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -256,8 +286,17 @@ def main():
         print("probe done", file=sys.stderr, flush=True)
         return
 
+    def table(tim):
+        return {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in tim.items()}
+
+    # Per-class breakdown on a short run with every class timed (two event records per launch).
+    # The timed run that gives `value` then carries events on the dominant class only.
+    print("bench: kernel breakdown", file=sys.stderr, flush=True)
+    _, _, tim_all = run_form(dgp.FP32, BREAKDOWN_STEPS, 1)
+    dom = max((k for k in tim_all if (k[:-5] if k.endswith("_fp32") else k) in
+               ("axis1_fwd", "fanout", "axis1_inv", "relax")), key=lambda k: tim_all[k][0])
     print("bench: timing precision form", file=sys.stderr, flush=True)
-    dt32, infos32, tim32 = run_form(dgp.FP32, args.steps, args.warmup)
+    dt32, infos32, tim32 = run_form(dgp.FP32, args.steps, args.warmup, [dom])
     passes32 = sum(i["passes"] for _, i in infos32)
     value = N ** 3 * passes32 / dt32
     res = {
@@ -283,13 +322,12 @@ def main():
             "resid": [i["resid"] for _, i in infos32],
             "ms_solve_per_step": sum(i["ms_total"] for _, i in infos32) / args.steps,
         },
-        "kernels_fp32_form": {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in tim32.items()},
+        "kernels_fp32_form": table(tim_all),
+        "kernels_note": "per-class HIP-event times from a %d-step run with every class timed" % BREAKDOWN_STEPS,
     }
     # dominant relaxation kernel of the timed region.  Passes launched after an element has
     # stopped exit at once; the per-launch figure divides the class time by the launches that
     # did a pass (FP32-phase passes for *_fp32 classes, FP64 passes otherwise).
-    dom = max((k for k in tim32 if (k[:-5] if k.endswith("_fp32") else k) in
-               ("axis1_fwd", "fanout", "axis1_inv", "relax")), key=lambda k: tim32[k][0])
     base = dom[:-5] if dom.endswith("_fp32") else dom
     elem = 4 if dom.endswith("_fp32") else 8
     bpl = algorithmic_bytes(base, N, elem)
@@ -301,7 +339,7 @@ def main():
                        "bytes_per_launch": bpl, "avg_us": avg_s * 1e6, "launches": tim32[dom][1],
                        "working_launches": working}
     gbs = {}
-    for k, (ms, cnt) in tim32.items():
+    for k, (ms, cnt) in tim_all.items():
         b = k[:-5] if k.endswith("_fp32") else k
         e = 4 if k.endswith("_fp32") else 8
         bb = algorithmic_bytes(b, N, e)
@@ -311,7 +349,8 @@ def main():
 
     if not args.no_fp64:
         print("bench: timing float64 form", file=sys.stderr, flush=True)
-        dt64, infos64, tim64 = run_form(dgp.FP64, args.steps, args.warmup)
+        _, _, tim64 = run_form(dgp.FP64, BREAKDOWN_STEPS, 1)
+        dt64, infos64, _ = run_form(dgp.FP64, args.steps, args.warmup, ["relax"])
         passes64 = sum(i["passes"] for _, i in infos64)
         t32 = sum(i["ms_total"] for _, i in infos32) / args.steps
         t64 = sum(i["ms_total"] for _, i in infos64) / args.steps
@@ -319,7 +358,7 @@ def main():
             "value": N ** 3 * passes64 / dt64, "ms_per_step": 1e3 * dt64 / args.steps,
             "passes_per_step": passes64 / args.steps, "ms_solve_per_step": t64,
             "status": [s for s, _ in infos64], "resid": [i["resid"] for _, i in infos64],
-            "kernels": {k: {"ms_total": v[0], "launches": v[1], "ms_avg": v[0] / v[1]} for k, v in tim64.items()},
+            "kernels": table(tim64),
         }
         res["fp32_polish_vs_fp64_solve_speedup"] = t64 / t32 if t32 > 0 else None
 

@@ -204,6 +204,10 @@ enum {
   DGP_T_NCLASS = 32
 };
 int dgp_timing_enable(dgp_plan* plan, int on);
+/* Restrict timing to the classes whose bits are set in class_mask (bit c for class c;
+ * all classes by default).  Each timed launch adds two event records to the stream, so a
+ * run that reports whole-step throughput times only the class it needs. */
+int dgp_timing_classes(dgp_plan* plan, unsigned int class_mask);
 /* total_ms / launches (either may be NULL) of one class since the last enable. */
 int dgp_timing_read(dgp_plan* plan, int cls, double* total_ms, long long* launches);
 

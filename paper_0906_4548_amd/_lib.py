@@ -15,7 +15,8 @@ EXPORTS = (
     "dgp_params_init", "dgp_plan_create", "dgp_plan_destroy", "dgp_plan_device_bytes",
     "dgp_deposit", "dgp_solve_field", "dgp_pm_forces", "dgp_step", "dgp_solve_field_backward",
     "dgp_deposit_backward", "dgp_power_spectrum", "dgp_power_spectrum_backward",
-    "dgp_fft_forward", "dgp_fft_inverse", "dgp_timing_enable", "dgp_timing_read", "dgp_last_error",
+    "dgp_fft_forward", "dgp_fft_inverse", "dgp_timing_enable", "dgp_timing_classes", "dgp_timing_read",
+    "dgp_last_error",
 )
 T_CLASSES = {"axis1_fwd": 0, "fanout": 1, "axis1_inv": 2, "relax": 3, "finalize": 4, "setup": 5,
              "deposit": 6, "forces": 7, "interp_kick": 8}
@@ -68,6 +69,7 @@ def load():
         "dgp_fft_forward": (ctypes.c_int, [vp, vp, vp, vp]),
         "dgp_fft_inverse": (ctypes.c_int, [vp, vp, vp, vp]),
         "dgp_timing_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+        "dgp_timing_classes": (ctypes.c_int, [vp, ctypes.c_uint]),
         "dgp_timing_read": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_longlong)]),
         "dgp_last_error": (ctypes.c_char_p, []),
     }

@@ -219,6 +219,7 @@ struct dgp_plan {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // live per-kernel timing (HIP events around launches on the caller's stream)
   bool timing = false;
+  unsigned int t_mask = 0xffffffffu;   // classes timed while timing is on
   struct Pend { hipEvent_t a, b; int cls; };
   std::vector<hipEvent_t> ev_pool;
   std::vector<Pend> pend;
@@ -244,7 +245,7 @@ struct Timed {
   int cls;
   hipEvent_t a = nullptr;
   Timed(dgp_plan* p, hipStream_t st, int c) : pl(p), s(st), cls(c) {
-    if (pl->timing && (a = ev_get(pl)) != nullptr) (void)hipEventRecord(a, s);
+    if (pl->timing && ((pl->t_mask >> cls) & 1u) && (a = ev_get(pl)) != nullptr) (void)hipEventRecord(a, s);
   }
   ~Timed() {
     if (!a) return;
@@ -1062,6 +1063,12 @@ extern "C" int dgp_timing_enable(dgp_plan* pl, int on) {
     pl->t_ms[i] = 0.0;
     pl->t_cnt[i] = 0;
   }
+  return DGP_OK;
+}
+
+extern "C" int dgp_timing_classes(dgp_plan* pl, unsigned int class_mask) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  pl->t_mask = class_mask;
   return DGP_OK;
 }
 

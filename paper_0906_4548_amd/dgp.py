@@ -161,6 +161,17 @@ class Plan:
         """Enable (and reset) or disable live HIP-event timing of the plan's kernel classes."""
         check(_lib.load().dgp_timing_enable(self.handle, int(bool(on))))
 
+    def timing_classes(self, names=None):
+        """Time only the given classes (names as returned by timing_read, e.g. 'relax_fp32');
+        None times every class."""
+        mask = 0xFFFFFFFF
+        if names is not None:
+            mask = 0
+            for nm in names:
+                base, off = (nm[:-5], _lib.T_FP32_OFFSET) if nm.endswith("_fp32") else (nm, 0)
+                mask |= 1 << (_lib.T_CLASSES[base] + off)
+        check(_lib.load().dgp_timing_classes(self.handle, ctypes.c_uint(mask)))
+
     def timing_read(self):
         """{class name: (total ms, launches)} including float32 classes as '<name>_fp32'."""
         out = {}
