@@ -454,10 +454,11 @@ struct Ws {
 static Ws<double> ws64(dgp_plan* pl) { return {pl->U, pl->S, pl->spec_u, pl->spec6, pl->partial, pl->groups64}; }
 static Ws<float> ws32(dgp_plan* pl) { return {pl->U32, pl->S32, pl->spec_u32, pl->spec6_32, pl->partial32, pl->groups32}; }
 
-// S and the linear guess from delta (float64).  The axis-0/1 spectrum of delta stays in
-// spectral field 6, where the PM step's force computation picks it up.
+// S and the linear guess from delta (float64; S32 / U32 receive their float32 roundings when
+// given).  The axis-0/1 spectrum of delta stays in spectral field 6, where the PM step's
+// force computation picks it up.
 static int setup_source(dgp_plan* pl, const dgp_params* p, const double* delta, Ws<double>& w, bool want_linear,
-                        hipStream_t s) {
+                        hipStream_t s, float* S32 = nullptr, float* U32 = nullptr) {
   const int n = pl->n, B = pl->batch;
   const size_t fs = (size_t)B * pl->hs;
   const SpecCoef cf = spec_coef(pl, p);
@@ -466,8 +467,8 @@ static int setup_source(dgp_plan* pl, const dgp_params* p, const double* delta, 
   TRY(fwd3<double>(pl, delta, dspec, B, nullptr, s));
   launch_p3<double>(n, SPEC_SOURCE, dspec, fs, 1, w.spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
   launch_p2<double>(n, w.spec6, 2, B, +1, nullptr, s);
-  launch_p1_inv<double>(n, w.spec6, w.S, B, nullptr, s);
-  if (want_linear) launch_p1_inv<double>(n, w.spec6 + fs, w.U, B, nullptr, s);
+  launch_p1_inv<double>(n, w.spec6, w.S, B, nullptr, s, S32);
+  if (want_linear) launch_p1_inv<double>(n, w.spec6 + fs, w.U, B, nullptr, s, U32);
   LAUNCHCHK();
   return DGP_OK;
 }
@@ -558,8 +559,7 @@ static int status_rank(int st) { return st == DGP_OK ? 0 : (st == DGP_NOT_CONVER
 template <typename T>
 static int collect_enqueue(dgp_plan* pl, Ws<T>& w, double* u_state, hipStream_t s) {
   const int B = pl->batch;
-  launch_take_result<T>(pl->ctl, w.U, B, pl->n3, u_state, s);
-  launch_absmean<double>(pl->n3, u_state, B, pl->red, pl->vec, pl->vec + B, s);
+  launch_take_result<T>(pl->ctl, w.U, B, pl->n3, u_state, pl->red, pl->vec + B, s);
   HIPCHK(hipMemcpyAsync(pl->means_host, pl->vec + B, sizeof(double) * B, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(pl->ctl_host, pl->ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
   LAUNCHCHK();
@@ -662,13 +662,14 @@ int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
   Ws<double> w = ws64(pl);
   // the source (and the linear guess) are formed once in float64: phase 2 needs them
   // exact, and phase 1 takes their rounding, which is closer than a float32 evaluation
-  TRY(setup_source(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s));
-  launch_convert<float>(B * n3, w.S, 0, w32.S, s);
-  if (p->init == DGP_INIT_LINEAR) {
-    launch_convert<float>(B * n3, w.U, 0, w32.U, s);
-  } else if (p->init == DGP_INIT_WARM) {
+  // the float64 initial guess stays in the float64 phase's first buffer (the warm start of
+  // phase 2 if phase 1 accepts the initial guess as it is)
+  TRY(setup_source(pl, p, delta, w, p->init == DGP_INIT_LINEAR, s, w32.S, w32.U));
+  if (p->init == DGP_INIT_WARM) {
+    HIPCHK(hipMemcpyAsync(w.U, u_state, sizeof(double) * B * n3, hipMemcpyDeviceToDevice, s));
     launch_convert<float>(B * n3, u_state, 0, w32.U, s);
-  } else {
+  } else if (p->init == DGP_INIT_ZERO) {
+    HIPCHK(hipMemsetAsync(w.U, 0, sizeof(double) * B * n3, s));
     HIPCHK(hipMemsetAsync(w32.U, 0, sizeof(float) * B * n3, s));
   }
   // eps = <|S|> of the float64 source; it stays in the control blocks for both phases

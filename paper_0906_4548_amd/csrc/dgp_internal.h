@@ -132,7 +132,8 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 template <typename T>
 void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ctl, hipStream_t s);
 template <typename T>
-void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s);
+void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s,
+                   float* out32 = nullptr);   // out32: optional float32 copy of out
 // nf fields, each [batch][H][N][N]; DIR -1 forward, +1 inverse
 template <typename T>
 void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, hipStream_t s);
@@ -164,9 +165,11 @@ void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s)
 // the latest iterate if the phase was still running) converted into dst[B][n3], then the
 // control re-initialised for the float64 phase with the float32 counts kept
 void launch_handoff(SolveCtl* ctl, const float* U32, int batch, size_t n3, double* dst, hipStream_t s);
-// the returned iterate of every element, as float64, into dst[B][n3]
+// the returned iterate of every element, as float64, into dst[B][n3], and its mean into
+// mean[B] (scratch: absmean_scratch_doubles(n3, batch) doubles)
 template <typename T>
-void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, hipStream_t s);
+void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, double* scratch,
+                        double* mean, hipStream_t s);
 
 // per-batch means of the two columns of [batch][groups][2] partial sums
 void launch_pair_means(const double* part, int groups, size_t n3, int batch, double* out0, double* out1,

@@ -100,7 +100,7 @@ k_p1_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restr
 template <typename T, int N>
 __global__ void __launch_bounds__((Geo<T, N>::kP1))
 k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw,
-         const SolveCtl* __restrict__ ctl) {
+         const SolveCtl* __restrict__ ctl, float* __restrict__ out32) {
   using P = typename Geo<T, N>::P;
   constexpr int R = P::R;
   using G = AxisTile<T, N, R>;
@@ -139,6 +139,12 @@ k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restr
   T* dst = out + (size_t)b * N * N * N + (size_t)i1 * N + i2;
 #pragma unroll
   for (int q = 0; q < R; ++q) *reinterpret_cast<cx<T>*>(dst + (size_t)(t + q * TT) * N * N) = v[q];
+  if (out32) {   // optional float32 rounding of the same output
+    float* d32 = out32 + (size_t)b * N * N * N + (size_t)i1 * N + i2;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      *reinterpret_cast<float2*>(d32 + (size_t)(t + q * TT) * N * N) = make_float2(float(v[q].x), float(v[q].y));
+  }
 }
 
 // ------------------------------------------------------------------ axis 1 (strided complex columns, in place)
@@ -458,10 +464,11 @@ static void p1_fwd_n(const T* in, cx<T>* out, int batch, const SolveCtl* ctl, co
   hipLaunchKernelGGL((k_p1_fwd<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
 }
 template <typename T, int N>
-static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, const cx<T>* tw, float* out32,
+                     hipStream_t s) {
   using G = AxisTile<T, N, Geo<T, N>::R>;
   dim3 grid(N / (2 * G::kTP), N, batch);
-  hipLaunchKernelGGL((k_p1_inv<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
+  hipLaunchKernelGGL((k_p1_inv<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl, out32);
 }
 template <typename T, int N>
 static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
@@ -523,9 +530,9 @@ void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ct
 #undef C
 }
 template <typename T>
-void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s) {
+void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s, float* out32) {
   const cx<T>* tw = twiddles<T>(n);
-#define C(NN) p1_inv_n<T, NN>(in, out, batch, ctl, tw, s)
+#define C(NN) p1_inv_n<T, NN>(in, out, batch, ctl, tw, out32, s)
   DGP_DISPATCH_N(n, C)
 #undef C
 }
@@ -562,8 +569,8 @@ int p3_row_groups(int n) {   // row groups of the float64 axis-2 pass (the P(k) 
 
 template void launch_p1_fwd<double>(int, const double*, cx<double>*, int, const SolveCtl*, hipStream_t);
 template void launch_p1_fwd<float>(int, const float*, cx<float>*, int, const SolveCtl*, hipStream_t);
-template void launch_p1_inv<double>(int, const cx<double>*, double*, int, const SolveCtl*, hipStream_t);
-template void launch_p1_inv<float>(int, const cx<float>*, float*, int, const SolveCtl*, hipStream_t);
+template void launch_p1_inv<double>(int, const cx<double>*, double*, int, const SolveCtl*, hipStream_t, float*);
+template void launch_p1_inv<float>(int, const cx<float>*, float*, int, const SolveCtl*, hipStream_t, float*);
 template void launch_p2<double>(int, cx<double>*, int, int, int, const SolveCtl*, hipStream_t);
 template void launch_p2<float>(int, cx<float>*, int, int, int, const SolveCtl*, hipStream_t);
 template void launch_p3<double>(int, SpecMode, const cx<double>*, size_t, int, cx<double>*, size_t, int, int,

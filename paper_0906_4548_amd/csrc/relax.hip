@@ -510,12 +510,12 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   }
 }
 
-// Convergence control: one workgroup of 256 threads walks the batch.
-__global__ void __launch_bounds__(256)
+// Convergence control: one workgroup of 1024 threads walks the batch (per element: strided
+// partial sums, wavefront shuffles, a fixed-order sum over the 16 wavefronts).
+__global__ void __launch_bounds__(1024)
 k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict__ ctl, SolveCfg cfg,
            int* __restrict__ n_active) {
-  __shared__ double sr[256];
-  __shared__ double sb[256];
+  __shared__ double sr[16], sb[16];
   __shared__ int active;
   if (threadIdx.x == 0) active = 0;
   const double n3 = double(cfg.n) * cfg.n * cfg.n;
@@ -523,21 +523,24 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
     __syncthreads();
     if (ctl[b].done) continue;
     double ar = 0.0, ab = 0.0;
-    for (int g = threadIdx.x; g < groups; g += 256) {
-      ar += partial[((size_t)b * groups + g) * 2];
-      ab += partial[((size_t)b * groups + g) * 2 + 1];
+    const double2* pb = reinterpret_cast<const double2*>(partial) + (size_t)b * groups;
+    for (int g = threadIdx.x; g < groups; g += 1024) {
+      const double2 v = pb[g];
+      ar += v.x;
+      ab += v.y;
     }
-    sr[threadIdx.x] = ar;
-    sb[threadIdx.x] = ab;
+    ar = wave_sum<64>(ar);
+    ab = wave_sum<64>(ab);
+    if ((threadIdx.x & 63) == 0) {
+      sr[threadIdx.x >> 6] = ar;
+      sb[threadIdx.x >> 6] = ab;
+    }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) {
-        sr[threadIdx.x] += sr[threadIdx.x + s];
-        sb[threadIdx.x] += sb[threadIdx.x + s];
-      }
-      __syncthreads();
-    }
     if (threadIdx.x == 0) {
+      for (int i = 1; i < 16; ++i) {
+        sr[0] += sr[i];
+        sb[0] += sb[i];
+      }
       SolveCtl& C = ctl[b];
       const double r = sr[0] / (n3 * C.eps);
       const int nbad = int(sb[0]);
@@ -691,7 +694,7 @@ int relax_groups(int n, int elem_bytes) {
 
 void launch_finalize(const double* partial, int groups, SolveCtl* ctl, const SolveCfg& cfg, int* n_active,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partial, groups, ctl, cfg, n_active);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, partial, groups, ctl, cfg, n_active);
 }
 
 __device__ void ctl_reset(SolveCtl& C) {
@@ -724,20 +727,45 @@ __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict_
   C.phase1_done = 1;
 }
 
+// -1: the float32 phase met its tolerance on the initial guess itself, whose float64 form
+// already sits in the float64 phase's first buffer
 __device__ __forceinline__ int handoff_buffer(const SolveCtl& C) {
   if (!C.done) return C.cur;
+  if (C.status == 0 && C.iters == 0) return -1;
   return (C.status == 0 && C.final_bad == 0) ? C.out : C.result;
 }
 
+// copies the selected buffer; with part != nullptr it also leaves per-workgroup sums of |x|
+// and x (the layout k_absmean_final reads)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_take_buffer(const SolveCtl* __restrict__ ctl, const T* __restrict__ U, int batch, size_t n3, double* __restrict__ dst,
-              int handoff) {
+              int handoff, double* __restrict__ part) {
   const int b = blockIdx.y;
   const int src = handoff ? handoff_buffer(ctl[b]) : ctl[b].result;
+  if (src < 0) return;   // (handoff only: no reduction is requested there)
   const T* in = U + ((size_t)src * batch + b) * n3;
   double* out = dst + (size_t)b * n3;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) out[i] = double(in[i]);
+  double sa = 0.0, sm = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const double v = double(in[i]);
+    out[i] = v;
+    sa += fabs(v);
+    sm += v;
+  }
+  if (!part) return;
+  sa = wave_sum<64>(sa);
+  sm = wave_sum<64>(sm);
+  __shared__ double ra[4], rm[4];
+  if ((threadIdx.x & 63) == 0) {
+    ra[threadIdx.x >> 6] = sa;
+    rm[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2] = ((ra[0] + ra[1]) + ra[2]) + ra[3];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = ((rm[0] + rm[1]) + rm[2]) + rm[3];
+  }
 }
 
 // keeps eps (the float64 source's) and records the float32 phase's counts
@@ -752,6 +780,11 @@ __global__ void k_ctl_phase2(SolveCtl* __restrict__ ctl, int batch) {
   ctl_reset(C);
 }
 
+static int absmean_groups(size_t n3) {
+  size_t g = (n3 + 255) / 256;
+  return int(g > 1024 ? 1024 : g);
+}
+
 static unsigned copy_groups(size_t n3) {
   const size_t g = (n3 + 255) / 256;
   return unsigned(g > 4096 ? 4096 : g);
@@ -759,26 +792,27 @@ static unsigned copy_groups(size_t n3) {
 
 void launch_handoff(SolveCtl* ctl, const float* U32, int batch, size_t n3, double* dst, hipStream_t s) {
   hipLaunchKernelGGL((k_take_buffer<float>), dim3(copy_groups(n3), batch), dim3(256), 0, s, ctl, U32, batch, n3, dst,
-                     1);
+                     1, nullptr);
   hipLaunchKernelGGL(k_ctl_phase2, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, batch);
 }
 
 template <typename T>
-void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL((k_take_buffer<T>), dim3(copy_groups(n3), batch), dim3(256), 0, s, ctl, U, batch, n3, dst, 0);
+void launch_take_result(const SolveCtl* ctl, const T* U, int batch, size_t n3, double* dst, double* scratch,
+                        double* mean, hipStream_t s) {
+  const int g = absmean_groups(n3);
+  hipLaunchKernelGGL((k_take_buffer<T>), dim3(g, batch), dim3(256), 0, s, ctl, U, batch, n3, dst, 0, scratch);
+  hipLaunchKernelGGL(k_absmean_final, dim3(batch), dim3(256), 0, s, scratch, g, n3, nullptr, mean);
 }
 
-template void launch_take_result<double>(const SolveCtl*, const double*, int, size_t, double*, hipStream_t);
-template void launch_take_result<float>(const SolveCtl*, const float*, int, size_t, double*, hipStream_t);
+template void launch_take_result<double>(const SolveCtl*, const double*, int, size_t, double*, double*, double*,
+                                         hipStream_t);
+template void launch_take_result<float>(const SolveCtl*, const float*, int, size_t, double*, double*, double*,
+                                        hipStream_t);
 
 void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s) {
   hipLaunchKernelGGL(k_ctl_init, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, eps, batch);
 }
 
-static int absmean_groups(size_t n3) {
-  size_t g = (n3 + 255) / 256;
-  return int(g > 1024 ? 1024 : g);
-}
 
 size_t absmean_scratch_doubles(size_t n3, int batch) { return (size_t)absmean_groups(n3) * batch * 2; }
 

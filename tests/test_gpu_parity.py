@@ -122,6 +122,25 @@ def test_solve_warm_zero_init_and_planar(dgp):
         assert st == 0 and info[0]["iters"] == 0
 
 
+@pytest.mark.parametrize("init", ["linear", "zero", "warm"])
+def test_precision_form_init_modes(dgp, init):
+    """The precision form from each initial guess meets the float64 tolerance and lands on
+    the oracle's solution; a warm start from the float64 answer needs no float32 pass."""
+    say("precision form init", init)
+    n, box = 32, 64.0
+    delta = inputs.lognormal_delta(n, box, 1.0, 21)
+    lam = calibrate_lambda(delta, box, 1.0)
+    u_ref, _ = fld.solve(delta, box, oracle_params(lam=lam, tol=1e-12, max_iter=100))
+    mode = {"linear": dgp.INIT_LINEAR, "zero": dgp.INIT_ZERO, "warm": dgp.INIT_WARM}[init]
+    with dgp.Plan(n, box, precision=dgp.FP32) as plan:
+        u = to_dev(u_ref) if init == "warm" else torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=lam, tol=1e-9, max_iter=100, init=mode), to_dev(delta), u)
+        assert st == 0 and info[0]["resid"] <= 1e-9
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= 1e-7
+        if init == "warm":
+            assert info[0]["passes"] - info[0]["passes_fp64"] <= 1
+
+
 def test_solve_bad_points_same_sequence(dgp):
     """w = 0 at z = 4 on deep voids: bad points, stop at the minimum residual (same decisions)."""
     say("solve bad points")
