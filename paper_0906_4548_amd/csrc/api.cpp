@@ -205,7 +205,8 @@ struct dgp_plan {
   // PM (batch 1)
   long long* grid = nullptr;         // [n3]
   double* delta = nullptr;           // [n3]
-  double* mesh3 = nullptr;           // [3][n3]
+  double* mesh3 = nullptr;           // [3][n3] force mesh (float64 plans)
+  float* mesh3_32 = nullptr;         // [3][n3] force mesh (precision-form plans)
   // power spectrum
   double* bin_tab = nullptr;         // thresholds + coefficients
   double* bin_partial = nullptr;
@@ -332,7 +333,7 @@ static int plan_alloc(dgp_plan* pl) {
     TRY(dalloc(pl, &pl->U32, 3 * B * n3));
     TRY(dalloc(pl, &pl->S32, B * n3));
     TRY(dalloc(pl, &pl->spec_u32, B * hs));
-    TRY(dalloc(pl, &pl->spec6_32, 6 * B * hs));
+    TRY(dalloc(pl, &pl->spec6_32, 8 * B * hs));   // as spec6: fields 6, 7 for the PM step's force mesh
     pl->groups32 = relax_groups(pl->n, 4);
     TRY(dalloc(pl, &pl->partial32, B * pl->groups32 * 2));
   }
@@ -347,7 +348,10 @@ static int plan_alloc(dgp_plan* pl) {
   if (B == 1) {
     TRY(dalloc(pl, &pl->grid, n3));
     TRY(dalloc(pl, &pl->delta, n3));
-    TRY(dalloc(pl, &pl->mesh3, 3 * n3));
+    if (pl->precision == DGP_FP32)
+      TRY(dalloc(pl, &pl->mesh3_32, 3 * n3));
+    else
+      TRY(dalloc(pl, &pl->mesh3, 3 * n3));
   }
   TRY(dalloc(pl, &pl->bin_tab, 129 + 128 * B));
   TRY(dalloc(pl, &pl->bin_partial, (size_t)p3_row_groups(pl->n) * B * 2 * 128));
@@ -733,17 +737,48 @@ extern "C" int dgp_deposit(dgp_plan* pl, const void* pos, int pos_is_fp32, long 
   return DGP_OK;
 }
 
-// force mesh g = -(c/H0)^2 grad phi, [3][n3] into mesh3 (and phi into phi_n when given).
-// delta_ready: spectral field 6 already holds the axis-0/1 spectrum of delta (left there by
-// the solve's setup on the same delta).
-static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u, double* mesh3,
-                      double* phi_n, bool delta_ready, hipStream_t s) {
+// force mesh g = -(c/H0)^2 grad phi, [3][n3] (and phi into phi_n when given).  A float64
+// plan forms it in float64 into mesh3; a precision-form plan forms it with float32 transforms
+// into mesh3_32 (the field solve itself stays polished to the float64 tolerance).
+// delta_ready: spectral field 6 already holds the float64 axis-0/1 spectrum of delta (left
+// there by the solve's setup on the same delta).
+static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u, double* phi_n,
+                      bool delta_ready, hipStream_t s) {
   Timed tm(pl, s, DGP_T_FORCES);
   const int n = pl->n;
-  const size_t fs = pl->hs;
+  const size_t fs = pl->hs, n3 = pl->n3;
   SpecCoef cf = spec_coef(pl, p);
   cf.with_phi = phi_n ? 1 : 0;
   const bool use_u = p->force_mode == DGP_FORCE_NLDGP;
+  const int nout = phi_n ? 4 : 3;
+  if (pl->precision == DGP_FP32) {
+    cx<float>* fin = pl->spec6_32 + 6 * fs;   // delta, then u
+    float* tmp = pl->U32;                     // the solve's float32 iterates are free here
+    if (delta_ready) {
+      launch_convert<float>(2 * fs, pl->spec6 + 6 * fs, 0, reinterpret_cast<float*>(fin), s);
+    } else {
+      launch_convert<float>(n3, delta, 0, tmp, s);
+      launch_p1_fwd<float>(n, tmp, fin, 1, nullptr, s);
+    }
+    if (use_u) {
+      launch_convert<float>(n3, u, 0, tmp + n3, s);
+      launch_p1_fwd<float>(n, tmp + n3, fin + fs, 1, nullptr, s);
+    }
+    if (!delta_ready)
+      launch_p2<float>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
+    else if (use_u)
+      launch_p2<float>(n, fin + fs, 1, 1, -1, nullptr, s);
+    launch_p3<float>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6_32, fs, nout, 1, cf, nullptr, nullptr, nullptr,
+                     nullptr, s);
+    launch_p2<float>(n, pl->spec6_32, nout, 1, +1, nullptr, s);
+    launch_p1_inv<float>(n, pl->spec6_32, pl->mesh3_32, 3, nullptr, s);
+    if (phi_n) {
+      launch_p1_inv<float>(n, pl->spec6_32 + 3 * fs, tmp, 1, nullptr, s);
+      launch_convert<double>(n3, tmp, 1, phi_n, s);
+    }
+    LAUNCHCHK();
+    return DGP_OK;
+  }
   cx<double>* fin = pl->spec6 + 6 * fs;   // delta, then u
   if (!delta_ready) launch_p1_fwd<double>(n, delta, fin, 1, nullptr, s);
   if (use_u) launch_p1_fwd<double>(n, u, fin + fs, 1, nullptr, s);
@@ -751,14 +786,19 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
     launch_p2<double>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
   else if (use_u)
     launch_p2<double>(n, fin + fs, 1, 1, -1, nullptr, s);
-  const int nout = phi_n ? 4 : 3;
   launch_p3<double>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6, fs, nout, 1, cf, nullptr, nullptr, nullptr,
                     nullptr, s);
   launch_p2<double>(n, pl->spec6, nout, 1, +1, nullptr, s);
-  launch_p1_inv<double>(n, pl->spec6, mesh3, 3, nullptr, s);
+  launch_p1_inv<double>(n, pl->spec6, pl->mesh3, 3, nullptr, s);
   if (phi_n) launch_p1_inv<double>(n, pl->spec6 + 3 * fs, phi_n, 1, nullptr, s);
   LAUNCHCHK();
   return DGP_OK;
+}
+
+// the plan's force mesh and its element type
+static const void* mesh_of(const dgp_plan* pl, int* fp32) {
+  *fp32 = pl->precision == DGP_FP32 ? 1 : 0;
+  return *fp32 ? static_cast<const void*>(pl->mesh3_32) : static_cast<const void*>(pl->mesh3);
 }
 
 extern "C" int dgp_pm_forces(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_state,
@@ -770,8 +810,10 @@ extern "C" int dgp_pm_forces(dgp_plan* pl, const dgp_params* p, const double* de
   if (!delta || !pos || !force || np < 1) return fail(DGP_E_INVALID, "delta, pos, force and np >= 1 are required");
   if (p->force_mode == DGP_FORCE_NLDGP && !u_state) return fail(DGP_E_INVALID, "u_state is required for nlDGP forces");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  TRY(force_mesh(pl, p, delta, u_state, pl->mesh3, phi_n, false, s));
-  launch_interp(pl->n, pl->box, pl->mesh3, pos, pos_is_fp32, np, force, s);
+  TRY(force_mesh(pl, p, delta, u_state, phi_n, false, s));
+  int mfp32 = 0;
+  const void* mesh = mesh_of(pl, &mfp32);
+  launch_interp(pl->n, pl->box, mesh, mfp32, pos, pos_is_fp32, np, force, s);
   LAUNCHCHK();
   return DGP_OK;
 }
@@ -791,7 +833,7 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
     TRY(solve_enqueue(pl, p, pl->delta, u_state, s));
     HIPCHK(hipEventRecord(pl->ev1, s));
   }
-  TRY(force_mesh(pl, p, pl->delta, u_state, pl->mesh3, nullptr, solve, s));
+  TRY(force_mesh(pl, p, pl->delta, u_state, nullptr, solve, s));
   const double a = p->a;
   const double e_n = hubble_E(p->omega_m0, a);
   const double a_h = a * std::exp(0.5 * dlna);
@@ -800,7 +842,9 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
   const double drift = dlna / (a_h * a_h * e_h);
   {
     Timed tm(pl, s, DGP_T_INTERP_KICK);
-    launch_interp_kick_drift(pl->n, pl->box, pl->mesh3, pos, vel, is_fp32, np, kick, drift, s);
+    int mfp32 = 0;
+    const void* mesh = mesh_of(pl, &mfp32);
+    launch_interp_kick_drift(pl->n, pl->box, mesh, mfp32, pos, vel, is_fp32, np, kick, drift, s);
   }
   LAUNCHCHK();
   HIPCHK(hipStreamSynchronize(s));

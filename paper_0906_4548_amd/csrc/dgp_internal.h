@@ -190,9 +190,10 @@ void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long 
                     hipStream_t s);
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s);
 void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
-void launch_interp(int n, double box, const double* mesh3, const void* pos, int pos_fp32, long long np,
+// mesh3: [3][n3] float64 (mesh_fp32 = 0) or float32 (1)
+void launch_interp(int n, double box, const void* mesh3, int mesh_fp32, const void* pos, int pos_fp32, long long np,
                    double* force, hipStream_t s);
-void launch_interp_kick_drift(int n, double box, const double* mesh3, void* pos, void* vel, int fp32,
+void launch_interp_kick_drift(int n, double box, const void* mesh3, int mesh_fp32, void* pos, void* vel, int fp32,
                               long long np, double kick, double drift, hipStream_t s);
 void launch_deposit_backward(int n, double box, const void* pos, int pos_fp32, long long np,
                              const double* grad_delta, double* grad_pos, hipStream_t s);

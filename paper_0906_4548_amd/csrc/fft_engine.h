@@ -260,6 +260,16 @@ __device__ __forceinline__ void fft(cx<T> (&v)[P::R], const cx<T>* __restrict__ 
   fft_stages<T, N, P, DIR, 0, 1>(v, tw, lds, t);
 }
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() fences every address
+// space, and on this architecture the load counter it must drain also counts outstanding
+// global loads, so a barrier inside a transform would wait for the next tile's prefetch;
+// with the fence restricted to LDS the prefetch stays in flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -276,7 +286,7 @@ struct LdsCol {
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[e * C + c] = v; }
   __device__ __forceinline__ void sync() const {
     if constexpr (WAVE) wave_sync();
-    else __syncthreads();
+    else lds_barrier();
   }
 };
 
@@ -293,7 +303,7 @@ struct LdsRow {
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[at(e)] = v; }
   __device__ __forceinline__ void sync() const {
     if constexpr (WAVE) wave_sync();
-    else __syncthreads();
+    else lds_barrier();
   }
 };
 

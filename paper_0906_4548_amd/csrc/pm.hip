@@ -140,7 +140,7 @@ __device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, const P (&x
       whi[threadIdx.x >> 6][d] = hi[d];
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     long long vol = 1;
     for (int d = 0; d < 3; ++d) {
@@ -155,7 +155,7 @@ __device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, const P (&x
     }
     sbox[6] = vol <= cap ? 1 : 0;
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int d = 0; d < 6; ++d) bx[d] = sbox[d];
   return sbox[6] != 0;
@@ -197,7 +197,7 @@ k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsi
   const int vol = bx[3] * bx[4] * bx[5];
   if (binned)
     for (int i = threadIdx.x; i < vol; i += 256) hist[i] = 0ull;
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < kDepPPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
@@ -227,7 +227,7 @@ k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsi
     }
   }
   if (!binned) return;
-  __syncthreads();
+  lds_barrier();
   for (int i = threadIdx.x; i < vol; i += 256) {
     const unsigned long long v = hist[i];
     if (v != 0ull) atomicAdd(&grid[box_cell(i, cr, bx, n)], v);
@@ -275,8 +275,8 @@ __device__ __forceinline__ void gather_corners(const Cic& c, const At& at, doubl
 }
 
 // interpolate a 3-component mesh [3][N^3] to particles
-template <typename P>
-__device__ __forceinline__ void gather3(const double* __restrict__ mesh3, size_t n3, int n, const Cic& c,
+template <typename M>
+__device__ __forceinline__ void gather3(const M* __restrict__ mesh3, size_t n3, int n, const Cic& c,
                                         double (&f)[3]) {
   gather_corners(
       c,
@@ -284,36 +284,36 @@ __device__ __forceinline__ void gather3(const double* __restrict__ mesh3, size_t
         const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
         const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
         const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
-        return mesh3[(size_t)k * n3 + (ix * n + iy) * n + iz];
+        return double(mesh3[(size_t)k * n3 + (ix * n + iy) * n + iz]);
       },
       f);
 }
 
-template <typename P>
+template <typename P, typename M>
 __global__ void __launch_bounds__(256)
-k_interp(const double* __restrict__ mesh3, const P* __restrict__ pos, long long np, int n, double scale,
+k_interp(const M* __restrict__ mesh3, const P* __restrict__ pos, long long np, int n, double scale,
          double* __restrict__ force) {
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= np) return;
   const Cic c = cic_of(pos, np, p, n, scale);
   double f[3];
-  gather3<P>(mesh3, (size_t)n * n * n, n, c, f);
+  gather3<M>(mesh3, (size_t)n * n * n, n, c, f);
   force[p] = f[0];
   force[np + p] = f[1];
   force[2 * np + p] = f[2];
 }
 
 // leapfrog with momenta at half steps: p += kick * g(x_n); x += drift * p; wrap into [0, L)
-template <typename P>
+template <typename P, typename M>
 __global__ void __launch_bounds__(256)
-k_interp_kick_drift(const double* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
+k_interp_kick_drift(const M* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
                     int n, double scale, double box, double kick, double drift) {
 #pragma clang fp contract(off)
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= np) return;
   const Cic c = cic_of(pos, np, p, n, scale);
   double f[3];
-  gather3<P>(mesh3, (size_t)n * n * n, n, c, f);
+  gather3<M>(mesh3, (size_t)n * n * n, n, c, f);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const size_t k = (size_t)d * np + p;
@@ -341,12 +341,12 @@ constexpr int kGatherPPT = kGatherChunk / 256;
 constexpr int kGatherCap = DGP_GATHER_BIN_CAP;
 static_assert(kGatherChunk % 256 == 0, "chunk must be a multiple of the workgroup size");
 
-template <typename P>
+template <typename P, typename M>
 __global__ void __launch_bounds__(256)
-k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
+k_interp_kick_drift_bin(const M* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
                         int n, double scale, double box, double kick, double drift) {
 #pragma clang fp contract(off)
-  __shared__ double fl[3 * kGatherCap];
+  __shared__ M fl[3 * kGatherCap];
   const size_t n3 = (size_t)n * n * n;
   const long long p0 = xcd_chunk() * kGatherChunk;
   // positions and velocities are loaded together up front and kept in registers
@@ -365,7 +365,7 @@ k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P
       fl[2 * kGatherCap + i] = mesh3[2 * n3 + g];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < kGatherPPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
@@ -376,11 +376,11 @@ k_interp_kick_drift_bin(const double* __restrict__ mesh3, P* __restrict__ pos, P
           cs[k],
           [&](int a, int b, int cc, int q) {
             const int li = ((off[k][0] + a - bx[0]) * bx[4] + (off[k][1] + b - bx[1])) * bx[5] + (off[k][2] + cc - bx[2]);
-            return fl[q * kGatherCap + li];
+            return double(fl[q * kGatherCap + li]);
           },
           f);
     } else {
-      gather3<P>(mesh3, n3, n, cs[k], f);
+      gather3<M>(mesh3, n3, n, cs[k], f);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -481,40 +481,58 @@ void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStr
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_strided(n3), batch), dim3(256), 0, s, x, n3, mean);
 }
 
-void launch_interp(int n, double box, const double* mesh3, const void* pos, int pos_fp32, long long np, double* force,
-                   hipStream_t s) {
+template <typename M>
+static void interp_m(int n, double box, const M* mesh3, const void* pos, int pos_fp32, long long np, double* force,
+                     hipStream_t s) {
   const double scale = double(n) / box;
   if (pos_fp32)
-    hipLaunchKernelGGL((k_interp<float>), dim3(grid_for(np)), dim3(256), 0, s, mesh3, static_cast<const float*>(pos),
-                       np, n, scale, force);
+    hipLaunchKernelGGL((k_interp<float, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
+                       static_cast<const float*>(pos), np, n, scale, force);
   else
-    hipLaunchKernelGGL((k_interp<double>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
+    hipLaunchKernelGGL((k_interp<double, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
                        static_cast<const double*>(pos), np, n, scale, force);
+}
+
+void launch_interp(int n, double box, const void* mesh3, int mesh_fp32, const void* pos, int pos_fp32, long long np,
+                   double* force, hipStream_t s) {
+  if (mesh_fp32)
+    interp_m(n, box, static_cast<const float*>(mesh3), pos, pos_fp32, np, force, s);
+  else
+    interp_m(n, box, static_cast<const double*>(mesh3), pos, pos_fp32, np, force, s);
 }
 
 #ifndef DGP_GATHER_BINNED
 #define DGP_GATHER_BINNED 1
 #endif
 
-void launch_interp_kick_drift(int n, double box, const double* mesh3, void* pos, void* vel, int fp32, long long np,
-                              double kick, double drift, hipStream_t s) {
+template <typename M>
+static void kick_m(int n, double box, const M* mesh3, void* pos, void* vel, int fp32, long long np, double kick,
+                   double drift, hipStream_t s) {
   const double scale = double(n) / box;
   if (DGP_GATHER_BINNED) {
     const unsigned g = unsigned((np + kGatherChunk - 1) / kGatherChunk);
     if (fp32)
-      hipLaunchKernelGGL((k_interp_kick_drift_bin<float>), dim3(g), dim3(256), 0, s, mesh3, static_cast<float*>(pos),
-                         static_cast<float*>(vel), np, n, scale, box, kick, drift);
+      hipLaunchKernelGGL((k_interp_kick_drift_bin<float, M>), dim3(g), dim3(256), 0, s, mesh3,
+                         static_cast<float*>(pos), static_cast<float*>(vel), np, n, scale, box, kick, drift);
     else
-      hipLaunchKernelGGL((k_interp_kick_drift_bin<double>), dim3(g), dim3(256), 0, s, mesh3,
+      hipLaunchKernelGGL((k_interp_kick_drift_bin<double, M>), dim3(g), dim3(256), 0, s, mesh3,
                          static_cast<double*>(pos), static_cast<double*>(vel), np, n, scale, box, kick, drift);
     return;
   }
   if (fp32)
-    hipLaunchKernelGGL((k_interp_kick_drift<float>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
+    hipLaunchKernelGGL((k_interp_kick_drift<float, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
                        static_cast<float*>(pos), static_cast<float*>(vel), np, n, scale, box, kick, drift);
   else
-    hipLaunchKernelGGL((k_interp_kick_drift<double>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
+    hipLaunchKernelGGL((k_interp_kick_drift<double, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
                        static_cast<double*>(pos), static_cast<double*>(vel), np, n, scale, box, kick, drift);
+}
+
+void launch_interp_kick_drift(int n, double box, const void* mesh3, int mesh_fp32, void* pos, void* vel, int fp32,
+                              long long np, double kick, double drift, hipStream_t s) {
+  if (mesh_fp32)
+    kick_m(n, box, static_cast<const float*>(mesh3), pos, vel, fp32, np, kick, drift, s);
+  else
+    kick_m(n, box, static_cast<const double*>(mesh3), pos, vel, fp32, np, kick, drift, s);
 }
 
 void launch_deposit_backward(int n, double box, const void* pos, int pos_fp32, long long np, const double* grad_delta,

@@ -39,19 +39,42 @@ const cx<T>* twiddles(int n);
 #ifndef DGP_RELAX_PRELOAD
 #define DGP_RELAX_PRELOAD 0
 #endif
+#ifndef DGP_RELAX_TWL
+#define DGP_RELAX_TWL 1
+#endif
+
+#ifndef DGP_RELAX_TP_F32
+#define DGP_RELAX_TP_F32 0
+#endif
+#ifndef DGP_RELAX_TP_F64
+#define DGP_RELAX_TP_F64 0
+#endif
+#ifndef DGP_RELAX_MINW_F32
+#define DGP_RELAX_MINW_F32 1
+#endif
+
+// axis-0 tile of the relaxation kernel: AxisTile with an optional number of column pairs
+template <typename T, int N, int R, int TPSET>
+struct RelaxTile {
+  static constexpr int kT = AxisTile<T, N, R>::kT;
+  static constexpr int kTP = TPSET > 0 ? (TPSET < N / 2 ? TPSET : N / 2) : AxisTile<T, N, R>::kTP;
+  static constexpr int kThreads = kTP * kT;
+};
 
 template <typename T, int N>
 struct RelaxGeo {
   using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
   static constexpr int R = P::R;
-  using G = AxisTile<T, N, R>;
+  using G = RelaxTile<T, N, R, (sizeof(T) == 4 ? DGP_RELAX_TP_F32 : DGP_RELAX_TP_F64)>;
+  // minimum wavefronts per SIMD the register allocation plans for (second launch bound)
+  static constexpr int kMinWaves = sizeof(T) == 4 ? DGP_RELAX_MINW_F32 : 1;
   // accumulators of the float32 form may be float32 (pointwise arithmetic in the
   // precision of the fields); the residual, discriminant and root stay float64
   using Acc = typename std::conditional<(sizeof(T) == 4 && DGP_RELAX_F32ACC), float, double>::type;
 };
 
 template <typename T, int N>
-__global__ void __launch_bounds__((RelaxGeo<T, N>::G::kThreads))
+__global__ void __launch_bounds__((RelaxGeo<T, N>::G::kThreads), (RelaxGeo<T, N>::kMinWaves))
 k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
         cx<T>* __restrict__ spec_u, double* __restrict__ partial, const double* __restrict__ mean_u, SolveCfg cfg,
         const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
@@ -78,6 +101,12 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   __shared__ double red[G::kThreads];
   __shared__ int redi[G::kThreads];
   LdsCol<T, TP> L{lds, c};
+  // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
+  // cached global loads at every stage (visible after the first barrier of the field loop)
+  __shared__ cx<T> twl[DGP_RELAX_TWL ? N : 1];
+  if constexpr (DGP_RELAX_TWL)
+    for (int i = threadIdx.x; i < N; i += G::kThreads) twl[i] = tw[i];
+  const cx<T>* twp = DGP_RELAX_TWL ? twl : tw;
 
   // software pipeline: the tile of field f+1 is fetched into registers while field f is transformed
   const size_t col = (size_t)b * H * N * N + (size_t)i1 * N + i2;
@@ -102,7 +131,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   cx<T> up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    __syncthreads();
+    lds_barrier();
     if constexpr (kPrefetch) {
 #pragma unroll
       for (int r = 0; r < NPF; ++r) {
@@ -119,7 +148,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
         lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (f < 5) {
       if (kPrefetch) fetch(f + 1);
     } else if (DGP_RELAX_PRELOAD) {
@@ -144,7 +173,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       }
       v[q] = mk(xa.x - xb.y, xa.y + xb.x);
     }
-    fft<T, N, P, +1>(v, tw, L, t);
+    fft<T, N, P, +1>(v, twp, L, t);
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -208,13 +237,13 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     v[q] = o;
   }
   // forward axis-0 transform of u^(n+1)
-  fft<T, N, P, -1>(v, tw, L, t);
-  __syncthreads();
+  fft<T, N, P, -1>(v, twp, L, t);
+  lds_barrier();
 #pragma unroll
   for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
   red[threadIdx.x] = abs_r;
   redi[threadIdx.x] = nbad;
-  __syncthreads();
+  lds_barrier();
   cx<T>* dst = spec_u + col;
   for (int k = t; k < H; k += TT) {
     const cx<T> zk = lds[k * TP + c];
@@ -228,7 +257,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       red[threadIdx.x] += red[threadIdx.x + s];
       redi[threadIdx.x] += redi[threadIdx.x + s];
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (threadIdx.x == 0) {
     const size_t g = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
@@ -297,7 +326,7 @@ struct LdsPair {
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[(e >> 1) * SP + 2 * c + (e & 1)] = v; }
   __device__ __forceinline__ void sync() const {
     if constexpr (WAVE) wave_sync();
-    else __syncthreads();
+    else lds_barrier();
   }
 };
 
@@ -375,7 +404,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   for (int f = 0; f < 6; ++f) {
     cx<T>* buf = lds + (f & 1) * W::kTile;
     stash(buf);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int e = t + q * TT;
@@ -476,7 +505,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
     redd[threadIdx.x >> 6] = abs_r;
     redi[threadIdx.x >> 6] = nbad;
   }
-  __syncthreads();
+  lds_barrier();
   // u^(n+1) out of tile 0 (coalesced); the spectrum into tile 1, column-major with one pad
   T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
   for (int idx = threadIdx.x; idx < N * TP; idx += NT) {
@@ -487,7 +516,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   cx<T>* zt = lds + W::kTile;
 #pragma unroll
   for (int q = 0; q < R; ++q) zt[c * (N + 1) + t + q * TT] = v[q];
-  __syncthreads();
+  lds_barrier();
   cx<T>* dst = spec_u + col0;
   for (int idx = threadIdx.x; idx < H * TP; idx += NT) {
     const int k = idx / TP, p = idx % TP;

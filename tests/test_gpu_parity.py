@@ -296,6 +296,31 @@ def test_step_particle_orders(dgp, case):
         assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= 1e-10
 
 
+def test_step_precision_form(dgp):
+    """PM step of a precision-form plan (float32 transforms, float64 polish, float32 force
+    mesh) against the float64 oracle step."""
+    say("step precision form")
+    n, box, a, dlna = 32, 64.0, 0.5, 0.005
+    pos, psi = inputs.zeldovich_load(n, box, 13, block=8)
+    c = cos.coefficients(OM0, a)
+    vel = a * a * c.E * cos.omega_m_of_a(OM0, a) ** 0.55 * psi
+    _, delta = pm.deposit(pos, n, box)
+    lam = calibrate_lambda(delta, box, 1.78)
+    op = oracle_params(lam=lam, tol=1e-10)
+    x_ref, v_ref, u_ref, _ = pm.step(pos, vel, None, a, dlna, box, n, op, OM0)
+    with dgp.Plan(n, box, precision=dgp.FP32) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.step(gpu_params(dgp, lam=lam, tol=1e-10), tp, tv, u, dlna)
+        assert st == 0 and info["resid"] <= 1e-10
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= 1e-8
+        dv = tv.cpu().numpy() - vel
+        assert rel_l2(dv, v_ref - vel) <= 1e-5
+        dx = (tp.cpu().numpy() - pos + box / 2) % box - box / 2
+        dx_ref = (x_ref - pos + box / 2) % box - box / 2
+        assert rel_l2(dx, dx_ref) <= 1e-5
+
+
 def test_step_bad_point_regime_same_decisions(dgp):
     """r_nl = 10 on a particle load: the relaxation meets bad points in voids and stops at its
     minimum residual (Sec. III C); GPU and oracle take the same decisions (parity of this regime is
