@@ -83,7 +83,9 @@ typedef struct {
   int nonlocal;        /* 1 keeps the sqrt(-lap) and lap^{-1/2} terms (paper), 0 drops them */
   int force_mode;      /* dgp_force_mode used by dgp_pm_forces / dgp_step */
   int check_every;     /* passes between host reads of the convergence flags (>= 1; default 4) */
-  int reserved;
+  int spherical;       /* 1: spherical approximation (Eqs. FullDGP2sph, SphPoi) instead of the full
+                          solve: u is the first w = 1/3 update from u = 0, a local function of the
+                          source (info: iters 1, passes 0, resid -1 = not evaluated); 0: full solve */
 } dgp_params;
 
 /* Per-batch-element report of a solve (host memory, one per batch element). */
@@ -210,6 +212,24 @@ int dgp_timing_enable(dgp_plan* plan, int on);
 int dgp_timing_classes(dgp_plan* plan, unsigned int class_mask);
 /* total_ms / launches (either may be NULL) of one class since the last enable. */
 int dgp_timing_read(dgp_plan* plan, int cls, double* total_ms, long long* launches);
+
+/* Multi-step PM run (Sec. III A time stepping, Sec. III D): n_steps leapfrog steps of dlna
+ * starting at scale factor a_start.  Step k runs at a_k = a_start exp(k dlna) with the
+ * background coefficients of params recomputed for a_k (the other fields of params are used
+ * as given).  While a_k < a_switch the force law is the linearised DGP one (DGP_FORCE_LDGP, no
+ * field solve, as the paper does at early times); from the first step with a_k >= a_switch on
+ * it is params->force_mode, and every nonlinear solve after the first starts from the previous
+ * step's field (warm start).  pos, vel, u_state as for dgp_step; info: n_steps entries (or
+ * NULL).  Returns the worst step status, or a negative error (the run stops at the first). */
+int dgp_run(dgp_plan* plan, const dgp_params* params, void* pos, void* vel, int is_fp32, long long np,
+            double a_start, double dlna, int n_steps, double a_switch, double* u_state, dgp_info* info,
+            void* stream);
+
+/* Convergence history of the last solve of batch element b: resid[i] = <|R|>/eps of the
+ * iterate evaluated by pass i and bad[i] = bad-point fraction of the update that pass computed
+ * (Sec. III C, Fig. 3).  For the precision form this is the float64 phase.  Either array may
+ * be NULL; returns the number of entries written (at most cap), or a negative error. */
+int dgp_solve_history(dgp_plan* plan, int b, double* resid, double* bad, int cap);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* dgp_last_error(void);

@@ -168,3 +168,30 @@ def step(pos, vel, u_state, a, dlna, box, n, prm, omega_m0, mode=FORCE_NLDGP):
     force, _ = pm_forces(delta, u, pos, box, prm, omega_m0, a, mode)
     x, v = kick_drift(pos, vel, force, a, dlna, omega_m0, box)
     return x, v, u, info
+
+
+def run(pos, vel, a_start, dlna, n_steps, a_switch, box, n, omega_m0, lam, tol, max_iter=100, w=1.0 / 3.0,
+        spherical=False):
+    """n_steps PM steps from a_start (Sec. III A time stepping; Sec. III D: the linearised DGP
+    Poisson equation at early times, the full nonlinear solve from a_switch on).  Step k runs at
+    a_k = a_start exp(k dlna) with the coefficients of a_k; each nonlinear solve after the first
+    starts from the previous step's field.  spherical: the spherical approximation (Eq. SphPoi)
+    replaces the full solve.  Returns (pos, vel, u, [SolveInfo or None per step])."""
+    u = None
+    infos = []
+    for k in range(n_steps):
+        a = a_start * math.exp(k * dlna)
+        prm = fld.SolveParams.from_cosmology(omega_m0, a, lam=lam, w=w, tol=tol, max_iter=max_iter)
+        if a < a_switch:
+            pos, vel, _, _ = step(pos, vel, None, a, dlna, box, n, prm, omega_m0, mode=FORCE_LDGP)
+            infos.append(None)
+        elif spherical:
+            _, delta = deposit(pos, n, box)
+            u = fld.spherical_first_update(delta, box, prm)
+            force, _ = pm_forces(delta, u, pos, box, prm, omega_m0, a, FORCE_NLDGP)
+            pos, vel = kick_drift(pos, vel, force, a, dlna, omega_m0, box)
+            infos.append(None)
+        else:
+            pos, vel, u, info = step(pos, vel, u, a, dlna, box, n, prm, omega_m0)
+            infos.append(info)
+    return pos, vel, u, infos

@@ -627,8 +627,23 @@ static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
 int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s);
 
 // Enqueue a solve in the plan's form; ends with collect_enqueue (no final synchronisation).
+static int solve_spherical(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s);
+
 static int solve_enqueue(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s) {
+  if (p->spherical) return solve_spherical(pl, p, delta, u_state, s);
   return pl->precision == DGP_FP32 ? solve32_polish(pl, p, delta, u_state, s) : solve64(pl, p, delta, u_state, s);
+}
+
+// Spherical approximation (Eqs. FullDGP2sph, SphPoi): the source in float64, then the first
+// w = 1/3 update from u = 0, which at u = 0 is a pointwise function of S (the nonlocal linear
+// terms enter through S, as in the paper's spherical runs).
+static int solve_spherical(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, hipStream_t s) {
+  Ws<double> w = ws64(pl);
+  const int B = pl->batch;
+  TRY(setup_source(pl, p, delta, w, false, s));
+  launch_absmean<double>(pl->n3, w.S, B, pl->red, pl->vec, nullptr, s);
+  launch_spherical(pl->n3, B, w.S, w.U, p->alpha, p->lambda, pl->partial, pl->ctl, pl->vec, s);
+  return collect_enqueue<double>(pl, w, u_state, s);
 }
 
 extern "C" int dgp_solve_field(dgp_plan* pl, const dgp_params* p, const double* delta, double* u_state, double* c_out,
@@ -1100,6 +1115,51 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
 }
 
 // ------------------------------------------------------------------ live kernel timing
+extern "C" int dgp_solve_history(dgp_plan* pl, int b, double* resid, double* bad, int cap) {
+  if (!pl || b < 0 || b >= pl->batch || cap < 0) return fail(DGP_E_INVALID, "bad plan, batch index or capacity");
+  const SolveCtl& C = pl->ctl_host[b];   // as left by the last solve's final synchronisation
+  int m = std::min(std::min(C.passes, kMaxHist), cap);
+  for (int i = 0; i < m; ++i) {
+    if (resid) resid[i] = C.hist[i];
+    if (bad) bad[i] = C.hist_bad[i];
+  }
+  return m;
+}
+
+extern "C" int dgp_run(dgp_plan* pl, const dgp_params* p, void* pos, void* vel, int is_fp32, long long np,
+                       double a_start, double dlna, int n_steps, double a_switch, double* u_state, dgp_info* info,
+                       void* stream) {
+  if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
+  TRY(check_params(p));
+  if (n_steps < 0 || !(a_start > 0.0) || !std::isfinite(a_start) || !std::isfinite(dlna) || !std::isfinite(a_switch))
+    return fail(DGP_E_INVALID, "need n_steps >= 0, a_start > 0 and finite dlna, a_switch");
+  int worst = DGP_OK;
+  bool solved = false;
+  for (int k = 0; k < n_steps; ++k) {
+    const double a = a_start * std::exp(k * dlna);
+    dgp_params q;
+    TRY(dgp_params_init(&q, p->omega_m0, a));
+    q.lambda = p->lambda;
+    q.w = p->w;
+    q.omega_relax = p->omega_relax;
+    q.tol = p->tol;
+    q.max_iter = p->max_iter;
+    q.nonlocal = p->nonlocal;
+    q.check_every = p->check_every;
+    q.spherical = p->spherical;
+    const bool early = a < a_switch;
+    q.force_mode = early ? DGP_FORCE_LDGP : p->force_mode;
+    q.init = (q.force_mode == DGP_FORCE_NLDGP && solved) ? DGP_INIT_WARM : p->init;
+    dgp_info one{};
+    const int st = dgp_step(pl, &q, pos, vel, is_fp32, np, dlna, u_state, &one, stream);
+    if (st < 0) return st;
+    if (q.force_mode == DGP_FORCE_NLDGP) solved = true;
+    if (info) info[k] = one;
+    if (status_rank(st) > status_rank(worst)) worst = st;
+  }
+  return worst;
+}
+
 extern "C" int dgp_timing_enable(dgp_plan* pl, int on) {
   if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
   timing_flush(pl);

@@ -65,7 +65,8 @@ struct SolveCtl {
   double resid_min;
   double bad_frac;
   double mean_u;    // <u> of the current iterate (from its k = 0 mode)
-  double hist[kMaxHist];
+  double hist[kMaxHist];       // r of the iterate evaluated by pass n
+  double hist_bad[kMaxHist];   // bad-point fraction of the update computed by pass n
 };
 
 struct SolveCfg {
@@ -160,6 +161,12 @@ void launch_absmean(size_t n3, const T* x, int batch, double* scratch, double* a
 size_t absmean_scratch_doubles(size_t n3, int batch);
 // control blocks: eps from abs_mean[b], buffer roles reset
 void launch_ctl_init(SolveCtl* ctl, const double* eps, int batch, hipStream_t s);
+// spherical approximation (Eqs. FullDGP2sph, SphPoi): u = the first w = 1/3 update from u = 0,
+// u = 2 S / (alpha + sqrt(alpha^2 + (8/3) lam S)) (vertex where the discriminant is negative),
+// for [batch][n3] S into u; then the control blocks record a decided one-update solve
+// (per-workgroup bad counts go through `partial`, which must hold batch x 4096 x 2 doubles)
+void launch_spherical(size_t n3, int batch, const double* S, double* u, double alpha, double lam, double* partial,
+                      SolveCtl* ctl, const double* eps, hipStream_t s);
 // end of the float32 phase: per element, the warm start for float64 (the update of the
 // pass that met the switch tolerance unless it met bad points, else the checked iterate;
 // the latest iterate if the phase was still running) converted into dst[B][n3], then the

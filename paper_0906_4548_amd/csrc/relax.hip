@@ -18,6 +18,7 @@
 // A single-workgroup kernel then forms r = <|R|>/eps (Eq. normres) per batch
 // element and runs the stopping rules; kernels of later passes read the
 // per-element `done` flag and exit at once.
+#include <algorithm>
 #include <type_traits>
 
 #include "dgp_internal.h"
@@ -574,7 +575,10 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
       const double r = sr[0] / (n3 * C.eps);
       const int nbad = int(sb[0]);
       const int n = C.iters;
-      if (n < kMaxHist) C.hist[n] = r;
+      if (n < kMaxHist) {
+        C.hist[n] = r;
+        C.hist_bad[n] = double(nbad) / n3;
+      }
       C.passes += 1;
       bool done = false;
       if (r <= cfg.tol) {
@@ -742,7 +746,10 @@ __device__ void ctl_reset(SolveCtl& C) {
   C.resid_min = __builtin_huge_val();
   C.bad_frac = 0.0;
   C.mean_u = 0.0;
-  for (int i = 0; i < kMaxHist; ++i) C.hist[i] = -1.0;
+  for (int i = 0; i < kMaxHist; ++i) {
+    C.hist[i] = -1.0;
+    C.hist_bad[i] = -1.0;
+  }
 }
 
 __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, int batch) {
@@ -823,6 +830,68 @@ void launch_handoff(SolveCtl* ctl, const float* U32, int batch, size_t n3, doubl
   hipLaunchKernelGGL((k_take_buffer<float>), dim3(copy_groups(n3), batch), dim3(256), 0, s, ctl, U32, batch, n3, dst,
                      1, nullptr);
   hipLaunchKernelGGL(k_ctl_phase2, dim3((batch + 63) / 64), dim3(64), 0, s, ctl, batch);
+}
+
+// ------------------------------------------------------------------ spherical approximation
+__global__ void __launch_bounds__(256)
+k_spherical(size_t n3, const double* __restrict__ S, double* __restrict__ u, double alpha, double lam,
+            double* __restrict__ partial) {
+  const int b = blockIdx.y;
+  const double c4 = 4.0 * (1.0 - 1.0 / 3.0) * lam;
+  const double vertex = -alpha / (2.0 * (1.0 - 1.0 / 3.0) * lam);
+  const double* sb = S + (size_t)b * n3;
+  double* ub = u + (size_t)b * n3;
+  int nbad = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const double bp = sb[i];   // B' = S at u = 0 (Hessian and nonlocal terms vanish)
+    const double disc = alpha * alpha + c4 * bp;
+    if (disc < 0.0) {
+      ub[i] = vertex;
+      ++nbad;
+    } else {
+      ub[i] = 2.0 * bp / (alpha + sqrt(disc));
+    }
+  }
+  nbad = wave_sum<64>(nbad);
+  __shared__ int rb[4];
+  if ((threadIdx.x & 63) == 0) rb[threadIdx.x >> 6] = nbad;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    partial[(size_t)b * gridDim.x + blockIdx.x] = double(((rb[0] + rb[1]) + rb[2]) + rb[3]);
+}
+
+__global__ void __launch_bounds__(256)
+k_ctl_spherical(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, const double* __restrict__ partial,
+                int groups, size_t n3) {
+  const int b = blockIdx.x;
+  double nb = 0.0;
+  for (int g = threadIdx.x; g < groups; g += 256) nb += partial[(size_t)b * groups + g];
+  nb = wave_sum<64>(nb);
+  __shared__ double rb[4];
+  if ((threadIdx.x & 63) == 0) rb[threadIdx.x >> 6] = nb;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  SolveCtl& C = ctl[b];
+  ctl_reset(C);
+  C.eps = eps[b];
+  C.iters1 = 0;
+  C.passes1 = 0;
+  C.phase1_done = 1;
+  C.done = 1;
+  C.status = 0;
+  C.iters = 1;
+  C.result = 0;
+  C.resid = -1.0;       // not evaluated: the approximation is not a root of Eq. FullDGP2
+  C.resid_min = -1.0;
+  C.bad_frac = (((rb[0] + rb[1]) + rb[2]) + rb[3]) / double(n3);
+  C.hist_bad[0] = C.bad_frac;
+}
+
+void launch_spherical(size_t n3, int batch, const double* S, double* u, double alpha, double lam, double* partial,
+                      SolveCtl* ctl, const double* eps, hipStream_t s) {
+  const int g = int(std::min<size_t>(4096, (n3 + 255) / 256));
+  hipLaunchKernelGGL(k_spherical, dim3(g, batch), dim3(256), 0, s, n3, S, u, alpha, lam, partial);
+  hipLaunchKernelGGL(k_ctl_spherical, dim3(batch), dim3(256), 0, s, ctl, eps, partial, g, n3);
 }
 
 template <typename T>

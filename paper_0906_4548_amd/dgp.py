@@ -124,6 +124,27 @@ class Plan:
                                         _ptr(u_state, torch.float64, self.n3, "u_state"), infos, _stream()))
         return st, infos[0].as_dict()
 
+    def run(self, prm, pos, vel, u_state, a_start, dlna, n_steps, a_switch):
+        """dgp_run: n_steps PM steps from a_start (lDGP forces before a_switch, then the
+        plan's solve with warm starts).  Returns (worst status, [info dict per step])."""
+        npart = pos.shape[-1]
+        if vel.dtype != pos.dtype:
+            raise TypeError("pos and vel must share a dtype")
+        fp32 = 1 if pos.dtype == torch.float32 else 0
+        infos = (Info * max(1, int(n_steps)))()
+        st = check(_lib.load().dgp_run(self.handle, ctypes.byref(prm), _ptr(pos, None, 3 * npart, "pos"),
+                                       _ptr(vel, None, 3 * npart, "vel"), fp32, npart, float(a_start),
+                                       float(dlna), int(n_steps), float(a_switch),
+                                       _ptr(u_state, torch.float64, self.n3, "u_state"), infos, _stream()))
+        return st, [infos[k].as_dict() for k in range(int(n_steps))]
+
+    def history(self, b=0, cap=256):
+        """(residual per pass, bad-point fraction per pass) of the last solve of element b."""
+        r = (ctypes.c_double * cap)()
+        f = (ctypes.c_double * cap)()
+        m = check(_lib.load().dgp_solve_history(self.handle, int(b), r, f, int(cap)))
+        return np.array(r[:m]), np.array(f[:m])
+
     def solve_field_backward(self, prm, delta, u_star, grad_u, grad_delta):
         cnt = self.batch * self.n3
         infos = (Info * self.batch)()

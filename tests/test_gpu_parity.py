@@ -371,3 +371,92 @@ def test_invalid_arguments(dgp):
             with pytest.raises(dgp._lib.DGPError) as e:
                 plan.solve_field(gpu_params(dgp, **bad), d, u)
             assert e.value.code == -1
+
+
+# ---------------------------------------------------------------- multi-step driver, spherical mode, history
+def _run_case():
+    n, box = 32, 64.0
+    pos, psi = inputs.zeldovich_load(n, box, 17, block=8)
+    a0, dlna = 0.45, 0.05
+    c = cos.coefficients(OM0, a0)
+    vel = a0 * a0 * c.E * cos.omega_m_of_a(OM0, a0) ** 0.55 * psi
+    _, delta = pm.deposit(pos, n, box)
+    lam = calibrate_lambda(delta, box, 1.78, a=a0)
+    return n, box, pos, vel, a0, dlna, lam
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_run_against_oracle(dgp, prec):
+    """dgp_run: one linearised-DGP step before a_switch, three full solves after it (the second
+    and third warm-started), against the oracle's driver."""
+    say("run", prec)
+    n, box, pos, vel, a0, dlna, lam = _run_case()
+    x_ref, v_ref, u_ref, infos = pm.run(pos, vel, a0, dlna, 4, 0.47, box, n, OM0, lam, 1e-11)
+    assert infos[0] is None and all(i is not None and i.status == 0 for i in infos[1:])
+    precision = dgp.FP64 if prec == "fp64" else dgp.FP32
+    with dgp.Plan(n, box, precision=precision) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, steps = plan.run(dgp.params(OM0, a0, lam=lam, tol=1e-11, max_iter=100), tp, tv, u, a0, dlna, 4, 0.47)
+        assert st == 0 and len(steps) == 4
+        assert steps[0]["passes"] == 0 and all(s["resid"] <= 1e-11 for s in steps[1:])
+        if prec == "fp64":   # same decisions as the oracle, warm starts included
+            assert [s["iters"] for s in steps[1:]] == [i.iters for i in infos[1:]]
+        tol = 1e-9 if prec == "fp64" else 1e-5
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= (1e-9 if prec == "fp64" else 1e-8)
+        dx = (tp.cpu().numpy() - pos + box / 2) % box - box / 2
+        dx_ref = (x_ref - pos + box / 2) % box - box / 2
+        assert rel_l2(dx, dx_ref) <= tol
+        assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= tol
+
+
+def test_spherical_mode(dgp):
+    """spherical = 1: the first w = 1/3 update from zero (Eq. SphPoi) for a solve, and the
+    spherical-mode PM run, against the oracle."""
+    say("spherical")
+    n, box = 32, 64.0
+    delta = inputs.lognormal_delta(n, box, 1.0, 23)
+    lam = calibrate_lambda(delta, box, 3.0)
+    op = oracle_params(lam=lam)
+    u_ref = fld.spherical_first_update(delta, box, op)
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=lam, spherical=1), to_dev(delta), u)
+        assert st == 0 and info[0]["iters"] == 1 and info[0]["passes"] == 0 and info[0]["resid"] == -1.0
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= 1e-13
+        assert abs(info[0]["mean_u"] - u_ref.mean()) <= 1e-12 * np.max(np.abs(u_ref))
+    n, box, pos, vel, a0, dlna, lam = _run_case()
+    x_ref, v_ref, _, _ = pm.run(pos, vel, a0, dlna, 2, 0.0, box, n, OM0, lam, 1e-11, spherical=True)
+    with dgp.Plan(n, box) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, _ = plan.run(dgp.params(OM0, a0, lam=lam, spherical=1), tp, tv, u, a0, dlna, 2, 0.0)
+        assert st == 0
+        dx = (tp.cpu().numpy() - pos + box / 2) % box - box / 2
+        dx_ref = (x_ref - pos + box / 2) % box - box / 2
+        assert rel_l2(dx, dx_ref) <= 1e-10
+
+
+def test_solve_history(dgp):
+    """Residual and bad-fraction history per pass (Fig. 3 quantities): the w = 1/3 solve
+    contracts monotonically with no bad points; w = 0 on deep voids meets bad points."""
+    say("history")
+    n, box = 16, 32.0
+    delta = inputs.lognormal_delta(n, box, 1.0, 5)
+    lam = calibrate_lambda(delta, box, 1.0)
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(gpu_params(dgp, lam=lam, tol=1e-10, max_iter=100), to_dev(delta), u)
+        r, bad = plan.history()
+        assert st == 0 and len(r) == info[0]["passes"] == info[0]["iters"] + 1
+        assert r[-1] == info[0]["resid"] and np.all(np.diff(r) < 0) and np.all(bad == 0)
+        _, i_ref = fld.solve(delta, box, oracle_params(lam=lam, tol=1e-10, max_iter=100))
+        assert abs(r[-1] - i_ref.resid) <= 1e-6 * i_ref.resid
+    n, box = 16, 32.0
+    delta = inputs.lognormal_delta(n, box, 1.5, 21)   # the bad-point case of the same-sequence test
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        p = dgp.params(OM0, 0.2, lam=1.0, w=0.0, tol=1e-12, max_iter=60, init=dgp.INIT_ZERO)
+        st, info = plan.solve_field(p, to_dev(delta), u)
+        r, bad = plan.history()
+        assert st == 2 and np.max(bad) > 0 and len(r) == info[0]["passes"]

@@ -577,3 +577,27 @@ def test_cic_adjoints_against_fd():
             assert abs(fi - gpi[d, pidx]) < 1e-6 * max(1.0, abs(fi))
     # mesh adjoint: <interp(mesh), gout> = <mesh, gm>
     assert abs(np.sum(pm.cic_interpolate(mesh, pos, box) * gout) - np.sum(mesh * gm)) < 1e-10
+
+
+def test_run_schedule_and_switch():
+    """The oracle's multi-step driver: step k at a_start e^(k dlna), linearised DGP forces while
+    a_k < a_switch, then full solves warm-started from the previous step (checked against the
+    same sequence assembled by hand, and the warm start against a cold solve)."""
+    n, box = 8, 16.0
+    pos, psi = inputs.zeldovich_load(n, box, 4)
+    vel = 0.1 * psi
+    a0, dlna = 0.4, 0.1
+    _, delta = pm.deposit(pos, n, box)
+    lam = 0.5
+    x, v, u, infos = pm.run(pos, vel, a0, dlna, 3, a0 * np.exp(0.5 * dlna), box, n, OM0, lam, 1e-12)
+    assert infos[0] is None and infos[1].status == fld.STATUS_OK and infos[2].status == fld.STATUS_OK
+    prm = lambda a: fld.SolveParams.from_cosmology(OM0, a, lam=lam, tol=1e-12)  # noqa: E731
+    a = [a0 * np.exp(k * dlna) for k in range(3)]
+    x1, v1, _, _ = pm.step(pos, vel, None, a[0], dlna, box, n, prm(a[0]), OM0, mode=pm.FORCE_LDGP)
+    x2, v2, u2, _ = pm.step(x1, v1, None, a[1], dlna, box, n, prm(a[1]), OM0)
+    x3, v3, u3, i3 = pm.step(x2, v2, u2, a[2], dlna, box, n, prm(a[2]), OM0)
+    assert np.array_equal(x, x3) and np.array_equal(v, v3) and np.array_equal(u, u3)
+    _, d3 = pm.deposit(x2, n, box)
+    u_cold, _ = fld.solve(d3, box, prm(a[2]))
+    assert np.max(np.abs(u3 - u_cold)) <= 1e-9 * np.max(np.abs(u_cold))
+    assert i3.iters < infos[1].iters
