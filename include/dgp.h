@@ -225,6 +225,19 @@ int dgp_run(dgp_plan* plan, const dgp_params* params, void* pos, void* vel, int 
             double a_start, double dlna, int n_steps, double a_switch, double* u_state, dgp_info* info,
             void* stream);
 
+/* Diagnostics of a solved field u = lap C (host outputs; any output may be NULL):
+ * nonelliptic[B]: fraction of mesh points where Eq. FullDGP2 is not elliptic, i.e. where the
+ *   matrix of dF/d(h_ij), (2 lam u + alpha) I - 2 lam h, is not definite (Appendix, Eq.
+ *   EllipticMatrix; Hessians spectral, float64);
+ * pc_over_pm[B][nbins]: P_c / P_m with c = alpha eta / (3 (eta - 1)) u (Eq. cdef, Sec. IV) and
+ *   P_m the power of delta (needs delta), same binning as dgp_power_spectrum (0 in empty bins);
+ * delta_gradc[B][nbins]: Delta_gradC = 4 pi k^5 P_C(k) (Eq. DGradC) at the bin centres
+ *   kf (N/2)^((b + 1/2) / nbins), kf = 2 pi / L.
+ * Synchronises the stream.  Errors: DGP_E_INVALID for NULL plan / u_state, nbins outside
+ * [1, 128] when a spectrum is requested, or pc_over_pm without delta. */
+int dgp_diagnostics(dgp_plan* plan, const dgp_params* params, const double* delta, const double* u_state,
+                    double* nonelliptic, double* pc_over_pm, double* delta_gradc, int nbins, void* stream);
+
 /* Convergence history of the last solve of batch element b: resid[i] = <|R|>/eps of the
  * iterate evaluated by pass i and bad[i] = bad-point fraction of the update that pass computed
  * (Sec. III C, Fig. 3).  For the precision form this is the float64 phase.  Either array may

@@ -16,7 +16,7 @@ EXPORTS = (
     "dgp_deposit", "dgp_solve_field", "dgp_pm_forces", "dgp_step", "dgp_solve_field_backward",
     "dgp_deposit_backward", "dgp_power_spectrum", "dgp_power_spectrum_backward",
     "dgp_fft_forward", "dgp_fft_inverse", "dgp_timing_enable", "dgp_timing_classes", "dgp_timing_read",
-    "dgp_run", "dgp_solve_history", "dgp_last_error",
+    "dgp_run", "dgp_solve_history", "dgp_diagnostics", "dgp_last_error",
 )
 T_CLASSES = {"axis1_fwd": 0, "fanout": 1, "axis1_inv": 2, "relax": 3, "finalize": 4, "setup": 5,
              "deposit": 6, "forces": 7, "interp_kick": 8}
@@ -74,6 +74,7 @@ def load():
                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double, vp,
                                    ctypes.POINTER(Info), vp]),
         "dgp_solve_history": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, ctypes.c_int]),
+        "dgp_diagnostics": (ctypes.c_int, [vp, P(Params), vp, vp, vp, vp, vp, ctypes.c_int, vp]),
         "dgp_timing_read": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_longlong)]),
         "dgp_last_error": (ctypes.c_char_p, []),
     }

@@ -105,12 +105,56 @@ k_adj_update(size_t n3, const double* __restrict__ q, const double* __restrict__
   }
 }
 
+// Ellipticity test (Appendix, Eq. EllipticMatrix): at every point the matrix of dF/d(h_ij),
+// (2 lam u + alpha) I - 2 lam h, is definite (all eigenvalues of one sign) or not.  Sylvester's
+// criterion on the leading principal minors decides definiteness; per-workgroup counts of the
+// points that are not elliptic go to part[b][g][2] (second slot 0) for the mean reduction.
+__global__ void __launch_bounds__(256)
+k_nonelliptic(size_t n3, int batch, const double* __restrict__ u, const double* __restrict__ h5,
+              const double* __restrict__ mean_u, double lam, double alpha, double* __restrict__ part) {
+  const int b = blockIdx.y;
+  const size_t off = (size_t)b * n3, fs = (size_t)batch * n3;
+  const double ub = mean_u[b];
+  double cnt = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const size_t k = off + i;
+    const double uu = u[k];
+    const double h00 = h5[k], h11 = h5[fs + k], h01 = h5[2 * fs + k], h02 = h5[3 * fs + k], h12 = h5[4 * fs + k];
+    const double h22 = (uu - ub) - h00 - h11;
+    const double d = 2.0 * lam * uu + alpha, c = -2.0 * lam;
+    const double m00 = d + c * h00, m11 = d + c * h11, m22 = d + c * h22;
+    const double m01 = c * h01, m02 = c * h02, m12 = c * h12;
+    const double d1 = m00;
+    const double d2 = m00 * m11 - m01 * m01;
+    const double d3 = m00 * (m11 * m22 - m12 * m12) - m01 * (m01 * m22 - m12 * m02) + m02 * (m01 * m12 - m11 * m02);
+    const bool elliptic = (d1 > 0.0 && d2 > 0.0 && d3 > 0.0) || (d1 < 0.0 && d2 > 0.0 && d3 < 0.0);
+    cnt += elliptic ? 0.0 : 1.0;
+  }
+  __shared__ double r[256];
+  r[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) r[threadIdx.x] += r[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2] = r[0];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = 0.0;
+  }
+}
+
 static int adj_groups(size_t n3) {
   size_t g = (n3 + 255) / 256;
   return int(g > 1024 ? 1024 : g);
 }
 
 int adjoint_groups(size_t n3) { return adj_groups(n3); }
+
+void launch_nonelliptic(size_t n3, int batch, const double* u, const double* h5, const double* mean_u, double lam,
+                        double alpha, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_nonelliptic, dim3(adj_groups(n3), batch), dim3(256), 0, s, n3, batch, u, h5, mean_u, lam, alpha,
+                     part);
+}
 
 void launch_adj_init(size_t n3, int batch, const double* g, const double* u, double* mu, double dscale, double alpha,
                      hipStream_t s) {

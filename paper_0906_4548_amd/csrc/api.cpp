@@ -1020,6 +1020,30 @@ extern "C" int dgp_fft_inverse(dgp_plan* pl, const double* spectrum, double* fie
 int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star, const double* grad_u,
                   double* grad_delta, dgp_info* info, hipStream_t s);
 
+// float64 work fields of the adjoint and the diagnostics, allocated on first use: [15][B][n3]
+static int ensure_adj(dgp_plan* pl) {
+  if (pl->adj) return DGP_OK;
+  const size_t bn = (size_t)pl->batch * pl->n3;
+  TRY(dalloc(pl, &pl->adj, 15 * bn));
+  TRY(dalloc(pl, &pl->adj_red, (size_t)adjoint_groups(pl->n3) * pl->batch * 2));
+  return DGP_OK;
+}
+
+// h00, h11, h01, h02, h12 of u (H5: [5][B][n3]; h22 follows from the trace identity) and <u>
+// into pl->mean_u, float64
+static int hessians(dgp_plan* pl, const dgp_params* p, const double* u, double* H5, hipStream_t s) {
+  const int n = pl->n, B = pl->batch;
+  const size_t fs = (size_t)B * pl->hs, bn = (size_t)B * pl->n3;
+  const SpecCoef cf = spec_coef(pl, p);
+  TRY(fwd3<double>(pl, u, pl->spec_u, B, nullptr, s));
+  launch_p3<double>(n, SPEC_FANOUT6, pl->spec_u, fs, 1, pl->spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, nullptr,
+                    s);
+  launch_p2<double>(n, pl->spec6, 6, B, +1, nullptr, s);
+  for (int f = 0; f < 5; ++f) launch_p1_inv<double>(n, pl->spec6 + f * fs, H5 + f * bn, B, nullptr, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
 extern "C" int dgp_solve_field_backward(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star,
                                         const double* grad_u, double* grad_delta, dgp_info* info, void* stream) {
   if (!pl) return fail(DGP_E_INVALID, "plan is NULL");
@@ -1034,10 +1058,7 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   (void)delta;   // S does not depend on delta; the solve's delta only fixed u*
   const int n = pl->n, B = pl->batch;
   const size_t n3 = pl->n3, fs = (size_t)B * pl->hs, bn = (size_t)B * n3;
-  if (!pl->adj) {
-    TRY(dalloc(pl, &pl->adj, 15 * bn));
-    TRY(dalloc(pl, &pl->adj_red, (size_t)adjoint_groups(n3) * B * 2));
-  }
+  TRY(ensure_adj(pl));
   double* H5 = pl->adj;
   double* P6 = pl->adj + 5 * bn;
   double* MU = pl->adj + 11 * bn;
@@ -1048,11 +1069,7 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   const double lam = p->lambda, w = p->w, alpha = p->alpha;
   const int G = adjoint_groups(n3);
   // Hessians of u* (h00, h11, h01, h02, h12) and <u*>
-  TRY(fwd3<double>(pl, u_star, pl->spec_u, B, nullptr, s));
-  launch_p3<double>(n, SPEC_FANOUT6, pl->spec_u, fs, 1, pl->spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, nullptr,
-                    s);
-  launch_p2<double>(n, pl->spec6, 6, B, +1, nullptr, s);
-  for (int f = 0; f < 5; ++f) launch_p1_inv<double>(n, pl->spec6 + f * fs, H5 + f * bn, B, nullptr, s);
+  TRY(hessians(pl, p, u_star, H5, s));
   launch_adj_init(n3, B, grad_u, u_star, MU, 2.0 * (1.0 - w) * lam, alpha, s);
   LAUNCHCHK();
   std::vector<int> done(B, 0), iters(B, 0);
@@ -1115,6 +1132,49 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
 }
 
 // ------------------------------------------------------------------ live kernel timing
+extern "C" int dgp_diagnostics(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_state,
+                               double* nonelliptic, double* pc_over_pm, double* delta_gradc, int nbins, void* stream) {
+  if (!pl || !u_state) return fail(DGP_E_INVALID, "plan and u_state are required");
+  TRY(check_params(p));
+  if ((pc_over_pm || delta_gradc) && (nbins < 1 || nbins > 128)) return fail(DGP_E_INVALID, "nbins must be in [1, 128]");
+  if (pc_over_pm && !delta) return fail(DGP_E_INVALID, "P_c/P_m needs delta");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int B = pl->batch;
+  if (nonelliptic) {
+    TRY(ensure_adj(pl));
+    TRY(hessians(pl, p, u_state, pl->adj, s));
+    launch_nonelliptic(pl->n3, B, u_state, pl->adj, pl->mean_u, p->lambda, p->alpha, pl->adj_red, s);
+    launch_pair_means(pl->adj_red, adjoint_groups(pl->n3), pl->n3, B, pl->vec, nullptr, s);
+    HIPCHK(hipMemcpyAsync(pl->means_host, pl->vec, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b) nonelliptic[b] = pl->means_host[b];
+  }
+  if (pc_over_pm) {   // Eq. cdef: c = alpha eta / (3 (eta - 1)) u
+    std::vector<double> su, cu, sd, cd;
+    TRY(power_impl(pl, p, u_state, 0, nbins, su, cu, s));
+    TRY(power_impl(pl, p, delta, 0, nbins, sd, cd, s));
+    const double coef = p->alpha * p->eta / (3.0 * (p->eta - 1.0));
+    for (size_t i = 0; i < (size_t)B * nbins; ++i) {
+      const double pu = cu[i] > 0 ? su[i] / cu[i] : 0.0, pd = cd[i] > 0 ? sd[i] / cd[i] : 0.0;
+      pc_over_pm[i] = pd > 0 ? coef * coef * pu / pd : 0.0;
+    }
+  }
+  if (delta_gradc) {   // Eq. DGradC: 4 pi k^5 P_C(k) at the bin centres kf (N/2)^((b + 1/2) / nbins)
+    std::vector<double> sc, cc;
+    TRY(power_impl(pl, p, u_state, 1, nbins, sc, cc, s));
+    const double norm = std::pow(pl->box, 3) / (double(pl->n3) * double(pl->n3));
+    const double kf = 2.0 * M_PI / pl->box;
+    for (int b = 0; b < B; ++b)
+      for (int i = 0; i < nbins; ++i) {
+        const size_t j = (size_t)b * nbins + i;
+        const double kc = kf * std::pow(pl->n / 2.0, (i + 0.5) / nbins);
+        const double pk = cc[j] > 0 ? sc[j] / cc[j] * norm : 0.0;
+        delta_gradc[j] = 4.0 * M_PI * std::pow(kc, 5) * pk;
+      }
+  }
+  return DGP_OK;
+}
+
 extern "C" int dgp_solve_history(dgp_plan* pl, int b, double* resid, double* bad, int cap) {
   if (!pl || b < 0 || b >= pl->batch || cap < 0) return fail(DGP_E_INVALID, "bad plan, batch index or capacity");
   const SolveCtl& C = pl->ctl_host[b];   // as left by the last solve's final synchronisation

@@ -192,6 +192,11 @@ void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, 
                        const double* h5, const double* mean_u, const double* mean_h22mu, const double* g, double lam,
                        double w, double alpha, double* part, hipStream_t s);
 
+// counts of points where Eq. FullDGP2 is not elliptic (Appendix), per workgroup into part
+// (adjoint_groups(n3) x batch x 2 doubles); launch_pair_means turns them into fractions
+void launch_nonelliptic(size_t n3, int batch, const double* u, const double* h5, const double* mean_u, double lam,
+                        double alpha, double* part, hipStream_t s);
+
 // PM kernels
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
                     hipStream_t s);

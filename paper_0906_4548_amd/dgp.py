@@ -171,6 +171,21 @@ class Plan:
             nbins, pk.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p), _stream()))
         return pk, cnt
 
+    def diagnostics(self, prm, delta, u, nbins=64):
+        """Diagnostics of a solved field u (Appendix, Eq. EllipticMatrix; Eqs. cdef, DGradC):
+        returns (non-elliptic fraction [batch], P_c/P_m [batch, nbins], Delta_gradC [batch, nbins])
+        as numpy arrays; P_c/P_m needs delta (None skips it)."""
+        ne = np.zeros(self.batch)
+        ratio = np.zeros((self.batch, nbins))
+        dgc = np.zeros((self.batch, nbins))
+        cnt = self.batch * self.n3
+        dptr = _ptr(delta, torch.float64, cnt, "delta") if delta is not None else None
+        check(_lib.load().dgp_diagnostics(
+            self.handle, ctypes.byref(prm), dptr, _ptr(u, torch.float64, cnt, "u"),
+            ne.ctypes.data_as(ctypes.c_void_p), ratio.ctypes.data_as(ctypes.c_void_p) if delta is not None else None,
+            dgc.ctypes.data_as(ctypes.c_void_p), int(nbins), _stream()))
+        return ne, (ratio if delta is not None else None), dgc
+
     def power_spectrum_backward(self, prm, field, grad_pk, grad_field, of_c=False):
         g = np.ascontiguousarray(grad_pk, dtype=np.float64).reshape(self.batch, -1)
         return check(_lib.load().dgp_power_spectrum_backward(

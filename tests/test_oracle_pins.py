@@ -14,7 +14,7 @@ import pytest
 from oracle import cosmology as cos
 from oracle import spectral as sp
 from oracle import field as fld
-from oracle import newton, pm, power, adjoint
+from oracle import newton, pm, power, adjoint, diagnostics
 from paper_0906_4548_amd import inputs
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -601,3 +601,32 @@ def test_run_schedule_and_switch():
     u_cold, _ = fld.solve(d3, box, prm(a[2]))
     assert np.max(np.abs(u3 - u_cold)) <= 1e-9 * np.max(np.abs(u_cold))
     assert i3.iters < infos[1].iters
+
+
+def test_nonelliptic_fraction_plane_wave_closed_form():
+    """u = A cos(2 pi m x / L): h_xx = u - <u> = u is the only Hessian component, so the
+    ellipticity matrix is diag(alpha, 2 lam u + alpha, 2 lam u + alpha) and the points with
+    2 lam u + alpha < 0 are not elliptic: a fraction arccos(alpha / (2 lam A)) / pi of a period."""
+    n, box, m = 64, 64.0, 1
+    prm = params(0.5, lam=1.0)
+    amp = 2.0 * prm.alpha / (2.0 * prm.lam)          # alpha / (2 lam A) = 1/2 -> fraction 1/3
+    x = (np.arange(n) + 0.25) * box / n              # offset grid: no point on the boundary
+    u = amp * np.cos(2.0 * np.pi * m * x / box)[:, None, None] * np.ones((n, n, n))
+    frac, _ = diagnostics.nonelliptic_fraction(u, box, prm)
+    assert frac == pytest.approx(np.arccos(prm.alpha / (2.0 * prm.lam * amp)) / np.pi, abs=1.0 / n)
+    assert diagnostics.nonelliptic_fraction(0.3 * u, box, prm)[0] == 0.0
+
+
+def test_pc_over_pm_is_one_in_the_linear_local_limit():
+    """Eq. deltaClin: without nonlinear and nonlocal terms, c = delta exactly, so P_c/P_m = 1 in
+    every populated bin; Delta_gradC follows Eq. DGradC from the binned P_C."""
+    n, box = 16, 64.0
+    delta = inputs.lognormal_delta(n, box, 0.5, 8)
+    prm = params(0.5, nonlocal_terms=False)
+    u = fld.linear_solution(fld.source(delta, box, prm)[1], box, prm)
+    ratio = diagnostics.pc_over_pm(delta, u, box, OM0, 0.5)
+    _, cnt, kc = power.power_spectrum(delta, box)
+    assert np.allclose(ratio[cnt > 0], 1.0, rtol=1e-12, atol=0)
+    dg = diagnostics.delta_gradc(u, box, prm)
+    pc, _, _ = power.power_spectrum(fld.c_from_u(u, box, prm), box)
+    assert np.allclose(dg, 4 * np.pi * kc ** 5 * pc)
