@@ -28,8 +28,12 @@ namespace dgp {
 template <typename T>
 const cx<T>* twiddles(int n);
 
+// FFT plans of the axis-0 transforms in the relaxation pass (0: radix 8, 1: radix 16, 2: radix 4)
 #ifndef DGP_PLAN_RELAX
 #define DGP_PLAN_RELAX 2
+#endif
+#ifndef DGP_PLAN_RELAX_F32
+#define DGP_PLAN_RELAX_F32 2
 #endif
 #ifndef DGP_RELAX_F32ACC
 #define DGP_RELAX_F32ACC 1
@@ -39,6 +43,11 @@ const cx<T>* twiddles(int n);
 #endif
 #ifndef DGP_RELAX_PRELOAD
 #define DGP_RELAX_PRELOAD 0
+#endif
+// float32: each thread loads the two spectral values of exactly the rows its transform
+// elements need (row e, or row N - e conjugated), skipping the LDS staging of the tile
+#ifndef DGP_RELAX_DIRECT
+#define DGP_RELAX_DIRECT 1
 #endif
 #ifndef DGP_RELAX_TWL
 #define DGP_RELAX_TWL 1
@@ -64,7 +73,7 @@ struct RelaxTile {
 
 template <typename T, int N>
 struct RelaxGeo {
-  using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
+  using P = typename PlanPick<N, (sizeof(T) == 4 ? DGP_PLAN_RELAX_F32 : DGP_PLAN_RELAX)>::type;
   static constexpr int R = P::R;
   using G = RelaxTile<T, N, R, (sizeof(T) == 4 ? DGP_RELAX_TP_F32 : DGP_RELAX_TP_F64)>;
   // minimum wavefronts per SIMD the register allocation plans for (second launch bound)
@@ -73,6 +82,83 @@ struct RelaxGeo {
   // precision of the fields); the residual, discriminant and root stay float64
   using Acc = typename std::conditional<(sizeof(T) == 4 && DGP_RELAX_F32ACC), float, double>::type;
 };
+
+// sum over the W lanes of a wavefront segment (butterfly order, deterministic)
+template <int W>
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+template <int W>
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+  return x;
+}
+
+// Per-point residual and update in float64 (Eqs. FullDGP2, Bwpara, nabla^2Cwpara).  The + root
+// 2 B' / (alpha + sqrt(Delta)) is formed without branches: the hardware estimates of
+// 1/sqrt(Delta) and of the reciprocal of the denominator (float64 instructions) are refined by
+// one Newton step each, sqrt(Delta) = Delta / sqrt(Delta) gets one Heron correction and the
+// quotient one residual correction (each correction squares the relative error).  Delta = 0 takes sqrt = 0, and a
+// negative Delta (a bad point) takes the vertex -alpha / (2 (1-w) lam).  Straight-line code
+// lets the compiler interleave the points of a thread.
+struct PointCoef {
+  double lam, w, alpha, gamma, omega, mu, vertex, c4;
+};
+
+__device__ __forceinline__ PointCoef point_coef(const SolveCfg& cfg, double mu) {
+  PointCoef k;
+  k.lam = cfg.lam;
+  k.w = cfg.w;
+  k.alpha = cfg.alpha;
+  k.gamma = cfg.gamma;
+  k.omega = cfg.omega;
+  k.mu = mu;
+  k.vertex = -cfg.alpha / (2.0 * (1.0 - cfg.w) * cfg.lam);
+  k.c4 = 4.0 * (1.0 - cfg.w) * cfg.lam;
+  return k;
+}
+
+// u: iterate, s: source, nf: nonlocal term, s2: sum of the squared Hessian entries other than
+// h22, h22m: -(h00 + h11) (h22 = h22m + u - <u> by the trace identity)
+__device__ __forceinline__ double relax_point(const PointCoef& k, double u, double s, double nf, double s2,
+                                              double h22m, double& abs_r, int& nbad) {
+  const double hz = h22m + (u - k.mu);
+  const double sh2 = s2 + hz * hz;
+  const double res = k.lam * (u * u - sh2) + k.alpha * u + k.gamma * nf - s;
+  abs_r += fabs(res);
+  const double bp = k.lam * (sh2 - k.w * u * u) - k.gamma * nf + s;
+  const double disc = k.alpha * k.alpha + k.c4 * bp;
+  nbad += disc < 0.0 ? 1 : 0;
+  double y = __builtin_amdgcn_rsq(disc);
+  y = y * (1.5 - (0.5 * disc) * (y * y));
+  double sq = disc * y;
+  sq = fma(0.5 * y, fma(-sq, sq, disc), sq);   // Heron correction of sqrt(Delta)
+  sq = disc > 0.0 ? sq : 0.0;
+  const double den = k.alpha + sq;
+  double r = __builtin_amdgcn_rcp(den);
+  r = r * (2.0 - den * r);
+  const double num = 2.0 * bp;
+  double x = num * r;
+  x = fma(r, fma(-den, x, num), x);
+  x = disc < 0.0 ? k.vertex : x;
+  if (k.omega != 1.0) x = (1.0 - k.omega) * u + k.omega * x;
+  return x;
+}
+
+template <int R, typename V, typename A>
+__device__ __forceinline__ void relax_points(const PointCoef& k, const V (&up)[R], const V (&spv)[R], const V (&nfv)[R],
+                                             const A (&s2)[R][2], const A (&h22)[R][2], double (&un)[R][2],
+                                             double& abs_r, int& nbad) {
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      un[q][j] = relax_point(k, double(j ? up[q].y : up[q].x), double(j ? spv[q].y : spv[q].x),
+                             double(j ? nfv[q].y : nfv[q].x), double(s2[q][j]), double(h22[q][j]), abs_r, nbad);
+}
 
 template <typename T, int N>
 __global__ void __launch_bounds__((RelaxGeo<T, N>::G::kThreads), (RelaxGeo<T, N>::kMinWaves))
@@ -91,6 +177,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   // the next field's tile is fetched into registers during the current transform
   // (float only: for double the staging registers make the compiler spill)
   constexpr bool kPrefetch = DGP_RELAX_PREFETCH && sizeof(T) == 4;
+  constexpr bool kDirect = DGP_RELAX_DIRECT && sizeof(T) == 4;
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
@@ -99,8 +186,8 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
   const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[LSZ];
-  __shared__ double red[G::kThreads];
-  __shared__ int redi[G::kThreads];
+  __shared__ double red[(G::kThreads + 63) / 64];
+  __shared__ int redi[(G::kThreads + 63) / 64];
   LdsCol<T, TP> L{lds, c};
   // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
   // cached global loads at every stage (visible after the first barrier of the field loop)
@@ -123,7 +210,22 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       }
     }
   };
-  if (kPrefetch) fetch(0);
+  // direct loads: element q of thread t is row e = t + q TT of the Hermitian-extended column
+  // pair; rows e > N/2 come from row N - e (conjugated when used)
+  cx<T> pd[R][2];
+  auto fetch_direct = [&](int f) {
+    const cx<T>* src = spec6 + f * fstride + col;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
+      const int r = e <= N / 2 ? e : N - e;
+      const float4 x = *reinterpret_cast<const float4*>(src + (size_t)r * N * N);
+      pd[q][0] = mk(T(x.x), T(x.y));
+      pd[q][1] = mk(T(x.z), T(x.w));
+    }
+  };
+  if constexpr (kDirect) fetch_direct(0);
+  else if (kPrefetch) fetch(0);
 
   Acc s2[R][2], h22[R][2];
   cx<T> v[R];
@@ -132,6 +234,28 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   cx<T> up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
+    if constexpr (kDirect) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int e = t + q * TT;
+        cx<T> xa = pd[q][0], xb = pd[q][1];
+        if (e > N / 2) {
+          xa = conjg(xa);
+          xb = conjg(xb);
+        }
+        if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
+        v[q] = mk(xa.x - xb.y, xa.y + xb.x);
+      }
+      if (f < 5) fetch_direct(f + 1);
+      else if (DGP_RELAX_PRELOAD) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const size_t off = (size_t)(t + q * TT) * N * N;
+          up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
+          spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
+        }
+      }
+    } else {
     lds_barrier();
     if constexpr (kPrefetch) {
 #pragma unroll
@@ -174,6 +298,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       }
       v[q] = mk(xa.x - xb.y, xa.y + xb.x);
     }
+    }
     fft<T, N, P, +1>(v, twp, L, t);
     if (f < 5) {
 #pragma unroll
@@ -197,43 +322,24 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     }
   }
   // pointwise residual and update; v holds Nf
-  const double lam = cfg.lam, w = cfg.w, alpha = cfg.alpha, gamma = cfg.gamma, omega = cfg.omega;
-  const double mu = mean_u[b];
-  const double vertex = -alpha / (2.0 * (1.0 - w) * lam);
-  const double c4 = 4.0 * (1.0 - w) * lam;
+  const PointCoef pc = point_coef(cfg, mean_u[b]);
   T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
   double abs_r = 0.0;
   int nbad = 0;
+  if (!DGP_RELAX_PRELOAD) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const size_t off = (size_t)(t + q * TT) * N * N;
-    if (!DGP_RELAX_PRELOAD) {
+    for (int q = 0; q < R; ++q) {
+      const size_t off = (size_t)(t + q * TT) * N * N;
       up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
       spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
     }
-    double un[2];
+  }
+  double un[R][2];
+  relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const double u = double(j ? up[q].y : up[q].x);
-      const double s = double(j ? spv[q].y : spv[q].x);
-      const double nf = double(j ? v[q].y : v[q].x);
-      const double hz = double(h22[q][j]) + (u - mu);
-      const double sh2 = double(s2[q][j]) + hz * hz;
-      const double res = lam * (u * u - sh2) + alpha * u + gamma * nf - s;
-      abs_r += fabs(res);
-      const double bp = lam * (sh2 - w * u * u) - gamma * nf + s;
-      const double disc = alpha * alpha + c4 * bp;
-      double x;
-      if (disc < 0.0) {
-        x = vertex;
-        ++nbad;
-      } else {
-        x = 2.0 * bp / (alpha + sqrt(disc));
-      }
-      if (omega != 1.0) x = (1.0 - omega) * u + omega * x;
-      un[j] = x;
-    }
-    const cx<T> o = mk(T(un[0]), T(un[1]));
+  for (int q = 0; q < R; ++q) {
+    const size_t off = (size_t)(t + q * TT) * N * N;
+    const cx<T> o = mk(T(un[q][0]), T(un[q][1]));
     *reinterpret_cast<cx<T>*>(uout + off) = o;
     v[q] = o;
   }
@@ -242,8 +348,13 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   lds_barrier();
 #pragma unroll
   for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
-  red[threadIdx.x] = abs_r;
-  redi[threadIdx.x] = nbad;
+  constexpr int WW = G::kThreads < 64 ? G::kThreads : 64;   // lanes of a (possibly partial) wavefront
+  abs_r = wave_sum<WW>(abs_r);
+  nbad = wave_sum<WW>(nbad);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = abs_r;
+    redi[threadIdx.x >> 6] = nbad;
+  }
   lds_barrier();
   cx<T>* dst = spec_u + col;
   for (int k = t; k < H; k += TT) {
@@ -252,21 +363,22 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     dst[(size_t)k * N * N] = mk(T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y));
     dst[(size_t)k * N * N + 1] = mk(T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x));
   }
-  // deterministic tree reduction of |R| and the bad count
-  for (int s = G::kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[threadIdx.x] += red[threadIdx.x + s];
-      redi[threadIdx.x] += redi[threadIdx.x + s];
-    }
-    lds_barrier();
-  }
+  // per-wavefront sums added in wavefront order (deterministic)
   if (threadIdx.x == 0) {
+    double sr = 0.0;
+    int sb = 0;
+#pragma unroll
+    for (int i = 0; i < (G::kThreads + 63) / 64; ++i) {
+      sr += red[i];
+      sb += redi[i];
+    }
     const size_t g = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     const size_t groups = (size_t)gridDim.x * gridDim.y;
-    partial[((size_t)b * groups + g) * 2] = red[0];
-    partial[((size_t)b * groups + g) * 2 + 1] = double(redi[0]);
+    partial[((size_t)b * groups + g) * 2] = sr;
+    partial[((size_t)b * groups + g) * 2 + 1] = double(sb);
   }
 }
+
 
 // ------------------------------------------------------------------ wave-local variant
 // Same pass as k_relax, restructured so that each axis-0 transform is carried by the
@@ -331,18 +443,6 @@ struct LdsPair {
   }
 };
 
-template <int W>
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
-  return x;
-}
-template <int W>
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
-  return x;
-}
 
 // (the second launch bound is the minimum number of wavefronts per SIMD to plan registers for)
 template <typename T, int N>
@@ -454,43 +554,24 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
     }
   }
   // pointwise residual and update (v holds Nf); u^(n+1) is staged in tile 0 (free since the last barrier)
-  const double lam = cfg.lam, w = cfg.w, alpha = cfg.alpha, gamma = cfg.gamma, omega = cfg.omega;
-  const double mu = mean_u[b];
-  const double vertex = -alpha / (2.0 * (1.0 - w) * lam);
-  const double c4 = 4.0 * (1.0 - w) * lam;
+  const PointCoef pc = point_coef(cfg, mean_u[b]);
   T* ust = reinterpret_cast<T*>(lds);
   double abs_r = 0.0;
   int nbad = 0;
+  if (!kPreload) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int e = t + q * TT;
-    if (!kPreload) {
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
       up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
       spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
     }
-    double un[2];
+  }
+  double un[R][2];
+  relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const double u = double(j ? up[q].y : up[q].x);
-      const double s = double(j ? spv[q].y : spv[q].x);
-      const double nf = double(j ? v[q].y : v[q].x);
-      const double hz = double(h22[q][j]) + (u - mu);
-      const double sh2 = double(s2[q][j]) + hz * hz;
-      const double res = lam * (u * u - sh2) + alpha * u + gamma * nf - s;
-      abs_r += fabs(res);
-      const double bp = lam * (sh2 - w * u * u) - gamma * nf + s;
-      const double disc = alpha * alpha + c4 * bp;
-      double x;
-      if (disc < 0.0) {
-        x = vertex;
-        ++nbad;
-      } else {
-        x = 2.0 * bp / (alpha + sqrt(disc));
-      }
-      if (omega != 1.0) x = (1.0 - omega) * u + omega * x;
-      un[j] = x;
-    }
-    const cx<T> o = mk(T(un[0]), T(un[1]));
+  for (int q = 0; q < R; ++q) {
+    const int e = t + q * TT;
+    const cx<T> o = mk(T(un[q][0]), T(un[q][1]));
     ust[e * (2 * TP + 1) + 2 * c] = o.x;
     ust[e * (2 * TP + 1) + 2 * c + 1] = o.y;
     v[q] = o;
