@@ -15,6 +15,8 @@ Other modes:
   --pmc-summary F W       turn the counter CSVs of two such passes (FETCH_SIZE, then
                           WRITE_SIZE) into the traffic summary kept under profiles/
   --trace-summary T       per-kernel duration table of a rocprofv3 kernel trace
+  --stages                per-stage times of a PM step on a 512^3 mesh with 512^3 float32
+                          particles (box 1024 Mpc/h), precision form and plain float64 form
 
 The solve runs in the precision form (float32 FFTs and pointwise storage,
 float64 residual / discriminant / root / reductions, float64 polish); the plain
@@ -41,7 +43,8 @@ import numpy as np  # noqa: E402
 
 N, BOX, SEED, A, OM0 = 256, 512.0, 3, 0.5, 0.27
 TOL = 1e-8
-RNL = 1.78          # nonlinear ratio lambda max|u_lin| / alpha (screened; see the design doc for the choice)
+RNL = 1.78          # nonlinear ratio lambda max|u_lin| / alpha: screened, and below the value (~3) at which
+                    # the deepest voids of a one-particle-per-cell load leave the discrete equation without a root
 DLNA = 0.005
 PEAK_HBM = 8.0e12   # bytes/s, MI355X
 BLOCK = 8           # particles stored in Lagrangian blocks of BLOCK^3
@@ -204,6 +207,60 @@ def algorithmic_bytes(cls, n, elem):
     }.get(cls)
 
 
+def stages_512(args, torch, dgp, inputs, dev):
+    """One JSON line: per-stage milliseconds per PM step at 512^3 (512^3 float32 particles in
+    Lagrangian 8^3 blocks, box 1024 Mpc/h, seed 4) for the precision form and the float64 form,
+    from the plan's HIP-event timing of every kernel class."""
+    n, box, seed, steps = 512, 1024.0, 4, max(1, min(args.steps, 3))
+    print("bench: building the 512^3 load", file=sys.stderr, flush=True)
+    pos_h, psi_h = inputs.zeldovich_load(n, box, seed, dtype=np.float32, block=BLOCK)
+    npart = pos_h.shape[1]
+    pos0 = torch.from_numpy(pos_h).to(dev)
+    prm0 = dgp.params(OM0, A)
+    growth = A * A * prm0.E * ((prm0.eta - 1.0) / prm0.eta) ** 0.55
+    vel0 = torch.from_numpy((growth * psi_h).astype(np.float32)).to(dev)
+    del pos_h, psi_h
+    with dgp.Plan(n, box) as p64:
+        delta = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
+        p64.deposit(pos0, None, delta)
+        ulin = torch.zeros_like(delta)
+        p64.solve_field(dgp.params(OM0, A, tol=0.0, max_iter=0), delta, ulin)
+        lam = RNL * prm0.alpha / float(ulin.abs().max())
+    del delta, ulin
+    torch.cuda.empty_cache()
+    out = {"mode": "stages", "config": {"workload": "Zel'dovich PM step, 512^3 mesh, 512^3 float32 particles, "
+                                                    "box 1024 Mpc/h, z=1, r_nl=%.2f, tol 1e-8" % RNL,
+                                        "mesh": n, "particles": npart, "lambda": lam, "steps": steps}}
+    for name, precision in (("precision_form", dgp.FP32), ("fp64_form", dgp.FP64)):
+        print("bench: stages of the %s" % name, file=sys.stderr, flush=True)
+        plan = dgp.Plan(n, box, precision=precision)
+        prm = dgp.params(OM0, A, lam=lam, tol=TOL, max_iter=200, init=dgp.INIT_LINEAR, check_every=8)
+        pos, vel = pos0.clone(), vel0.clone()
+        u = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
+        plan.step(prm, pos, vel, u, DLNA)
+        torch.cuda.synchronize()
+        plan.timing(True)
+        t0 = time.perf_counter()
+        infos = [plan.step(prm, pos, vel, u, DLNA) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tim = plan.timing_read()
+        plan.timing(False)
+        plan.close()
+        del pos, vel, u
+        torch.cuda.empty_cache()
+        out[name] = {
+            "ms_per_step": 1e3 * dt / steps,
+            "passes_per_step": sum(i["passes"] for _, i in infos) / steps,
+            "passes_fp64_per_step": sum(i["passes_fp64"] for _, i in infos) / steps,
+            "resid": [i["resid"] for _, i in infos],
+            "status": [st for st, _ in infos],
+            "stage_ms_per_step": {k: v[0] / steps for k, v in tim.items()},
+            "stage_launches_per_step": {k: v[1] / steps for k, v in tim.items()},
+        }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +271,8 @@ def main():
     ap.add_argument("--probe", action="store_true", help="short run for hardware-counter passes")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the calibrated traffic summary from two counter passes to stdout")
+    ap.add_argument("--stages", action="store_true",
+                    help="per-stage times of a 512^3 PM step with 512^3 float32 particles, both forms")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="write a per-kernel duration table from a rocprofv3 kernel trace to stdout")
     args = ap.parse_args()
@@ -233,6 +292,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stages:
+        stages_512(args, torch, dgp, inputs, dev)
+        return
     print("bench: building inputs", file=sys.stderr, flush=True)
     pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED, block=BLOCK)
     npart = pos_h.shape[1]
