@@ -73,9 +73,12 @@ struct RelaxTile {
 
 template <typename T, int N>
 struct RelaxGeo {
-  using P = typename PlanPick<N, (sizeof(T) == 4 ? DGP_PLAN_RELAX_F32 : DGP_PLAN_RELAX)>::type;
+  // at N >= 512 the spectral planes are 2 MB (float32) apart and a 128-byte row segment per
+  // plane streams poorly: float32 takes radix 8 and 16 column pairs (256-byte segments)
+  static constexpr bool kWide = sizeof(T) == 4 && N >= 512;
+  using P = typename PlanPick<N, (sizeof(T) == 4 ? (kWide ? 0 : DGP_PLAN_RELAX_F32) : DGP_PLAN_RELAX)>::type;
   static constexpr int R = P::R;
-  using G = RelaxTile<T, N, R, (sizeof(T) == 4 ? DGP_RELAX_TP_F32 : DGP_RELAX_TP_F64)>;
+  using G = RelaxTile<T, N, R, (sizeof(T) == 4 ? (kWide ? 16 : DGP_RELAX_TP_F32) : DGP_RELAX_TP_F64)>;
   // minimum wavefronts per SIMD the register allocation plans for (second launch bound)
   static constexpr int kMinWaves = sizeof(T) == 4 ? DGP_RELAX_MINW_F32 : 1;
   // accumulators of the float32 form may be float32 (pointwise arithmetic in the
@@ -412,10 +415,12 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 
 template <typename T, int N>
 struct RelaxWGeo {
-  using P = typename PlanPick<N, DGP_PLAN_RELAX>::type;
+  // float64 at N >= 512: radix 8 (one 512-point transform per wavefront) and 8 column pairs
+  static constexpr bool kWide = sizeof(T) == 8 && N >= 512;
+  using P = typename PlanPick<N, (kWide ? 0 : DGP_PLAN_RELAX)>::type;
   static constexpr int R = P::R;
   using G = AxisTile<T, N, R>;
-  static constexpr int kTPSet = sizeof(T) == 8 ? DGP_RELAXW_TP_F64 : DGP_RELAXW_TP_F32;
+  static constexpr int kTPSet = sizeof(T) == 8 ? (kWide ? 8 : DGP_RELAXW_TP_F64) : DGP_RELAXW_TP_F32;
   static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
   static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
   static constexpr int kMinWaves = sizeof(T) == 8 ? DGP_RELAXW_MINW_F64 : DGP_RELAXW_MINW_F32;
