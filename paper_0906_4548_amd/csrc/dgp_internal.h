@@ -92,7 +92,10 @@ struct ColTile {
   static constexpr int kT = N / R;
   static constexpr int kBase = 128 / int(sizeof(cx<T>));
   static constexpr int kWant0 = (64 / kT > kBase) ? 64 / kT : kBase;
-  static constexpr int kCap = (512 / kT > 1) ? 512 / kT : 1;
+  // up to 512 threads, or 1024 when that is what a 128-byte row segment takes (64-byte segments
+  // would split cache lines between workgroups on different XCDs)
+  static constexpr int kMaxThreads = (kBase * kT > 512 && kBase * kT <= 1024) ? kBase * kT : 512;
+  static constexpr int kCap = (kMaxThreads / kT > 1) ? kMaxThreads / kT : 1;
   static constexpr int kWant = (kWant0 > kCap) ? kCap : kWant0;
   static constexpr int kTY = (kWant > N) ? N : kWant;
   static constexpr int kThreads = kTY * kT;

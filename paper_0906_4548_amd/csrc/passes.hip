@@ -47,7 +47,8 @@ struct Geo {
   static constexpr bool kF32 = sizeof(T) == 4;
   using P = typename PlanPick<N, DGP_PLAN_P1>::type;
   using P2 = typename PlanPick<N, kF32 ? DGP_PLAN_P2_F32 : DGP_PLAN_P2_F64>::type;
-  using P3 = typename PlanPick<N, kF32 ? DGP_PLAN_P3_F32 : DGP_PLAN_P3_F64>::type;
+  // axis 2: a row's transform stays inside one wavefront (N/R <= 64): radix 8 from N = 512 on
+  using P3 = typename PlanPick<N, kF32 ? (N >= 512 ? 0 : DGP_PLAN_P3_F32) : DGP_PLAN_P3_F64>::type;
   static constexpr int R = P::R;
   static constexpr int kP1 = AxisTile<T, N, R>::kThreads;
   static constexpr int kP2 = ColTile<T, N, P2::R>::kThreads;
