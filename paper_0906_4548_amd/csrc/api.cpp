@@ -769,16 +769,11 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
   if (pl->precision == DGP_FP32) {
     cx<float>* fin = pl->spec6_32 + 6 * fs;   // delta, then u
     float* tmp = pl->U32;                     // the solve's float32 iterates are free here
-    if (delta_ready) {
+    if (delta_ready)
       launch_convert<float>(2 * fs, pl->spec6 + 6 * fs, 0, reinterpret_cast<float*>(fin), s);
-    } else {
-      launch_convert<float>(n3, delta, 0, tmp, s);
-      launch_p1_fwd<float>(n, tmp, fin, 1, nullptr, s);
-    }
-    if (use_u) {
-      launch_convert<float>(n3, u, 0, tmp + n3, s);
-      launch_p1_fwd<float>(n, tmp + n3, fin + fs, 1, nullptr, s);
-    }
+    else
+      launch_p1_fwd_from64(n, delta, fin, 1, nullptr, s);
+    if (use_u) launch_p1_fwd_from64(n, u, fin + fs, 1, nullptr, s);
     if (!delta_ready)
       launch_p2<float>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
     else if (use_u)

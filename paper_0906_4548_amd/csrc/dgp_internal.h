@@ -135,6 +135,8 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 
 template <typename T>
 void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ctl, hipStream_t s);
+// float32 axis-0 forward pass of a float64 real field (rounded on load)
+void launch_p1_fwd_from64(int n, const double* in, cx<float>* out, int batch, const SolveCtl* ctl, hipStream_t s);
 template <typename T>
 void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ctl, hipStream_t s,
                    float* out32 = nullptr);   // out32: optional float32 copy of out

@@ -60,9 +60,10 @@ __device__ __forceinline__ bool batch_done(const SolveCtl* ctl, int b) {
 }
 
 // ------------------------------------------------------------------ axis 0, forward (real -> complex)
-template <typename T, int N>
+// I: element type of the real input (float64 input to a float32 transform is rounded on load)
+template <typename T, int N, typename I = T>
 __global__ void __launch_bounds__((Geo<T, N>::kP1))
-k_p1_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
+k_p1_fwd(const I* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restrict__ tw,
          const SolveCtl* __restrict__ ctl) {
   using P = typename Geo<T, N>::P;
   constexpr int R = P::R;
@@ -75,10 +76,13 @@ k_p1_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restr
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
   const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[N * TP];
-  const T* src = in + (size_t)b * N * N * N + (size_t)i1 * N + i2;
+  const I* src = in + (size_t)b * N * N * N + (size_t)i1 * N + i2;
   cx<T> v[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = *reinterpret_cast<const cx<T>*>(src + (size_t)(t + q * TT) * N * N);
+  for (int q = 0; q < R; ++q) {
+    const cx<I> x = *reinterpret_cast<const cx<I>*>(src + (size_t)(t + q * TT) * N * N);
+    v[q] = mk(T(x.x), T(x.y));
+  }
   LdsCol<T, TP> L{lds, c};
   fft<T, N, P, -1>(v, tw, L, t);
   __syncthreads();
@@ -458,11 +462,11 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
 }
 
 // ------------------------------------------------------------------ launchers
-template <typename T, int N>
-static void p1_fwd_n(const T* in, cx<T>* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+template <typename T, int N, typename I = T>
+static void p1_fwd_n(const I* in, cx<T>* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
   using G = AxisTile<T, N, Geo<T, N>::R>;
   dim3 grid(N / (2 * G::kTP), N, batch);
-  hipLaunchKernelGGL((k_p1_fwd<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
+  hipLaunchKernelGGL((k_p1_fwd<T, N, I>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
 }
 template <typename T, int N>
 static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, const cx<T>* tw, float* out32,
@@ -527,6 +531,12 @@ template <typename T>
 void launch_p1_fwd(int n, const T* in, cx<T>* out, int batch, const SolveCtl* ctl, hipStream_t s) {
   const cx<T>* tw = twiddles<T>(n);
 #define C(NN) p1_fwd_n<T, NN>(in, out, batch, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+void launch_p1_fwd_from64(int n, const double* in, cx<float>* out, int batch, const SolveCtl* ctl, hipStream_t s) {
+  const cx<float>* tw = twiddles<float>(n);
+#define C(NN) p1_fwd_n<float, NN, double>(in, out, batch, ctl, tw, s)
   DGP_DISPATCH_N(n, C)
 #undef C
 }
