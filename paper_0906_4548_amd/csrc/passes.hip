@@ -42,6 +42,15 @@ namespace dgp {
 #ifndef DGP_PLAN_P3_F32
 #define DGP_PLAN_P3_F32 2
 #endif
+// Column tile of the axis-0 passes: AxisTile, widened from N = 512 on, where the planes are
+// 2 MB (float32) or 4 MB (float64) apart and 128-byte row segments per plane stream poorly.
+template <typename T, int N, int R>
+struct P1Tile {
+  using A = AxisTile<T, N, R>;
+  static constexpr int kTP = (N >= 512 && 2 * A::kTP * A::kT <= 1024 && 2 * A::kTP <= N / 2) ? 2 * A::kTP : A::kTP;
+  static constexpr int kT = A::kT, kThreads = kTP * kT;
+};
+
 template <typename T, int N>
 struct Geo {
   static constexpr bool kF32 = sizeof(T) == 4;
@@ -50,7 +59,7 @@ struct Geo {
   // axis 2: a row's transform stays inside one wavefront (N/R <= 64): radix 8 from N = 512 on
   using P3 = typename PlanPick<N, kF32 ? (N >= 512 ? 0 : DGP_PLAN_P3_F32) : DGP_PLAN_P3_F64>::type;
   static constexpr int R = P::R;
-  static constexpr int kP1 = AxisTile<T, N, R>::kThreads;
+  static constexpr int kP1 = P1Tile<T, N, R>::kThreads;
   static constexpr int kP2 = ColTile<T, N, P2::R>::kThreads;
   static constexpr int kP3 = RowTile<N, P3::R>::kThreads;
 };
@@ -67,7 +76,7 @@ k_p1_fwd(const I* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restr
          const SolveCtl* __restrict__ ctl) {
   using P = typename Geo<T, N>::P;
   constexpr int R = P::R;
-  using G = AxisTile<T, N, R>;
+  using G = P1Tile<T, N, R>;
   constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
   const int b = blockIdx.z;
   if (batch_done(ctl, b)) return;
@@ -108,7 +117,7 @@ k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restr
          const SolveCtl* __restrict__ ctl, float* __restrict__ out32) {
   using P = typename Geo<T, N>::P;
   constexpr int R = P::R;
-  using G = AxisTile<T, N, R>;
+  using G = P1Tile<T, N, R>;
   constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
   constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
   const int b = blockIdx.z;
@@ -464,14 +473,14 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
 // ------------------------------------------------------------------ launchers
 template <typename T, int N, typename I = T>
 static void p1_fwd_n(const I* in, cx<T>* out, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
-  using G = AxisTile<T, N, Geo<T, N>::R>;
+  using G = P1Tile<T, N, Geo<T, N>::R>;
   dim3 grid(N / (2 * G::kTP), N, batch);
   hipLaunchKernelGGL((k_p1_fwd<T, N, I>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl);
 }
 template <typename T, int N>
 static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, const cx<T>* tw, float* out32,
                      hipStream_t s) {
-  using G = AxisTile<T, N, Geo<T, N>::R>;
+  using G = P1Tile<T, N, Geo<T, N>::R>;
   dim3 grid(N / (2 * G::kTP), N, batch);
   hipLaunchKernelGGL((k_p1_inv<T, N>), grid, dim3(G::kThreads), 0, s, in, out, tw, ctl, out32);
 }
