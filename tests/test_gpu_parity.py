@@ -32,11 +32,13 @@ def say(*a):
 
 
 # ---------------------------------------------------------------- FFT
-@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_fft_forward_inverse(dgp, n, prec):
+    """Forward and inverse 3D transforms against numpy; 256 and 512 run the tile geometries
+    chosen for large meshes (one field at 512)."""
     say("fft", n, prec)
-    batch = 2
+    batch = 2 if n <= 256 else 1
     rng = np.random.default_rng(n)
     x = rng.standard_normal((batch, n, n, n))
     ref = np.fft.rfftn(x, axes=(2, 3, 1))        # real transform along axis 0 of each field
