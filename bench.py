@@ -124,11 +124,11 @@ def pmc_summary(fetch_csv, write_csv):
     lines = [
         "# HBM traffic per dispatch: PM step at 256^3 (FETCH_SIZE / WRITE_SIZE, calibrated)",
         "",
-        "Commands (repository root `$R`, one MI355X; one counter per pass):",
+        "Commands (repository root `$R`, any output directory `$OUT`, one MI355X; one counter per pass):",
         "",
-        "    cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $R/gpurun_out/pmc_fetch -o run -- "
+        "    cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- "
         "python3 $R/bench.py --probe",
-        "    cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $R/gpurun_out/pmc_write -o run -- "
+        "    cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- "
         "python3 $R/bench.py --probe",
         "    python3 bench.py --pmc-summary <pmc_fetch>/run_counter_collection.csv "
         "<pmc_write>/run_counter_collection.csv",
