@@ -384,6 +384,48 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
     if constexpr (MODE == SPEC_FANOUT6) {
       if (valid && k0 == 0 && k1 == 0 && t == 0 && mean_out != nullptr) mean_out[b] = double(v[0].x) * cf.inv_n3;
     }
+    if constexpr (MODE == SPEC_FANOUT6 && sizeof(T) == 4) {
+      // float32 fields: the six multipliers in float32 (reciprocal and reciprocal-sqrt estimates,
+      // the reciprocal refined by one Newton step), formed once per mode
+      const float ikbs = float(cf.inv_n3 / (cf.kappa * kf));
+      const float in3 = float(cf.inv_n3);
+      float a0[R], a1[R], a2[R], ik2[R], ikb[R];
+      bool z01[R], z02[R], z12[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        const float ms = float(m.msq);
+        float r = __builtin_amdgcn_rcpf(ms);
+        r = r * (2.0f - ms * r);
+        const bool nz = m.msq != 0;
+        ik2[q] = nz ? r * in3 : 0.0f;
+        ikb[q] = nz ? __builtin_amdgcn_rsqf(ms) * ikbs : 0.0f;
+        a0[q] = float(m.n0);
+        a1[q] = float(m.n1);
+        a2[q] = float(m.n2);
+        z01[q] = m.q0 || m.q1;
+        z02[q] = m.q0 || m.q2;
+        z12[q] = m.q1 || m.q2;
+      }
+#pragma unroll 1
+      for (int o = 0; o < 6; ++o) {
+        cx<T> w[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          float mult;
+          if (o == 0) mult = a0[q] * a0[q] * ik2[q];
+          else if (o == 1) mult = a1[q] * a1[q] * ik2[q];
+          else if (o == 2) mult = z01[q] ? 0.0f : a0[q] * a1[q] * ik2[q];
+          else if (o == 3) mult = z02[q] ? 0.0f : a0[q] * a2[q] * ik2[q];
+          else if (o == 4) mult = z12[q] ? 0.0f : a1[q] * a2[q] * ik2[q];
+          else mult = -ikb[q];
+          w[q] = scale(v[q], T(mult));
+        }
+        fft<T, N, P, +1>(w, tw, L, t);
+        store_row(out + o * out_stride, w);
+      }
+      return;
+    }
     constexpr int NOUT = (MODE == SPEC_FANOUT6) ? 6 : (MODE == SPEC_SOURCE) ? 2 : (MODE == SPEC_FORCES) ? 4 : 1;
 #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
