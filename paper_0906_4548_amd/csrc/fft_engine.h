@@ -44,6 +44,24 @@ __device__ __forceinline__ cx<T> conjg(cx<T> a) { return mk(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk(a.x * s, a.y * s); }
 
+// Streaming (nontemporal) global accesses for data that the same kernel will not touch again:
+// on gfx950 they keep the last-level cache from filling with lines that would only be written
+// back (stores) or evicted (loads) later, while the following pass reads its inputs.
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 x = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return mk(T(x.x), T(x.y));
+}
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 x;
+  x.x = v.x;
+  x.y = v.y;
+  __builtin_nontemporal_store(x, reinterpret_cast<v2*>(p));
+}
+
 // multiply by exp(DIR * i * pi/2 * m) for m = 1 (DIR=-1: -i), exact.
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> rot90(cx<T> a) {

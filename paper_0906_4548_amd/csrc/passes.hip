@@ -272,7 +272,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
   auto store_row = [&](cx<T>* dst, cx<T> (&w)[R]) {
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) dst[roff + t + q * TT] = w[q];
+      for (int q = 0; q < R; ++q) store_stream(&dst[roff + t + q * TT], w[q]);   // read by the next pass
     }
   };
   const double kf = cf.kf;

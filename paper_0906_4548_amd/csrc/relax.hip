@@ -214,7 +214,8 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     }
   };
   // direct loads: element q of thread t is row e = t + q TT of the Hermitian-extended column
-  // pair; rows e > N/2 come from row N - e (conjugated when used)
+  // pair; rows e > N/2 come from row N - e (conjugated when used); streaming loads (the last
+  // use of these spectra in the pass)
   cx<T> pd[R][2];
   auto fetch_direct = [&](int f) {
     const cx<T>* src = spec6 + f * fstride + col;
@@ -222,7 +223,8 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     for (int q = 0; q < R; ++q) {
       const int e = t + q * TT;
       const int r = e <= N / 2 ? e : N - e;
-      const float4 x = *reinterpret_cast<const float4*>(src + (size_t)r * N * N);
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      const f4 x = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src + (size_t)r * N * N));
       pd[q][0] = mk(T(x.x), T(x.y));
       pd[q][1] = mk(T(x.z), T(x.w));
     }
@@ -343,7 +345,8 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   for (int q = 0; q < R; ++q) {
     const size_t off = (size_t)(t + q * TT) * N * N;
     const cx<T> o = mk(T(un[q][0]), T(un[q][1]));
-    *reinterpret_cast<cx<T>*>(uout + off) = o;
+    if constexpr (kDirect) store_stream(reinterpret_cast<cx<T>*>(uout + off), o);   // read again next pass only
+    else *reinterpret_cast<cx<T>*>(uout + off) = o;
     v[q] = o;
   }
   // forward axis-0 transform of u^(n+1)
