@@ -105,8 +105,8 @@ k_p1_fwd(const I* __restrict__ in, cx<T>* __restrict__ out, const cx<T>* __restr
     // x_a(k) = (Z(k) + conj Z(N-k)) / 2,  x_b(k) = (Z(k) - conj Z(N-k)) / (2i)
     const cx<T> xa = mk(T(0.5) * (zk.x + zn.x), T(0.5) * (zk.y - zn.y));
     const cx<T> xb = mk(T(0.5) * (zk.y + zn.y), T(0.5) * (zn.x - zk.x));
-    dst[(size_t)k * N * N] = xa;
-    dst[(size_t)k * N * N + 1] = xb;
+    store_stream(&dst[(size_t)k * N * N], xa);   // read by the next pass
+    store_stream(&dst[(size_t)k * N * N + 1], xb);
   }
 }
 
@@ -152,7 +152,7 @@ k_p1_inv(const cx<T>* __restrict__ in, T* __restrict__ out, const cx<T>* __restr
   fft<T, N, P, +1>(v, tw, L, t);
   T* dst = out + (size_t)b * N * N * N + (size_t)i1 * N + i2;
 #pragma unroll
-  for (int q = 0; q < R; ++q) *reinterpret_cast<cx<T>*>(dst + (size_t)(t + q * TT) * N * N) = v[q];
+  for (int q = 0; q < R; ++q) store_stream(reinterpret_cast<cx<T>*>(dst + (size_t)(t + q * TT) * N * N), v[q]);
   if (out32) {   // optional float32 rounding of the same output
     float* d32 = out32 + (size_t)b * N * N * N + (size_t)i1 * N + i2;
 #pragma unroll

@@ -161,14 +161,15 @@ __device__ __forceinline__ bool chunk_box(const P* __restrict__ pos, const P (&x
   return sbox[6] != 0;
 }
 
-// the positions of the thread's particles in a chunk (unused slots past np left at 0)
+// the positions of the thread's particles in a chunk (unused slots past np left at 0); streaming
+// loads: a kernel reads each particle once
 template <int PPT, typename P>
 __device__ __forceinline__ void load_chunk(const P* __restrict__ a, long long np, long long p0, P (&xs)[PPT][3]) {
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) xs[k][d] = p < np ? a[(size_t)d * np + p] : P(0);
+    for (int d = 0; d < 3; ++d) xs[k][d] = p < np ? __builtin_nontemporal_load(&a[(size_t)d * np + p]) : P(0);
   }
 }
 
@@ -390,8 +391,8 @@ k_interp_kick_drift_bin(const M* __restrict__ mesh3, P* __restrict__ pos, P* __r
       x = x - box * floor(x / box);
       P xo = P(x);
       if (xo >= P(box)) xo = xo - P(box);
-      vel[i] = P(v);
-      pos[i] = xo;
+      __builtin_nontemporal_store(P(v), &vel[i]);   // streaming: read again only by the next step
+      __builtin_nontemporal_store(xo, &pos[i]);
     }
   }
 }
