@@ -5,8 +5,8 @@
 // kernel here is its last stage: for a tile of axis-0 columns it
 //   1. inverse-transforms along axis 0 the five Hessian spectra h00, h11, h01,
 //      h02, h12 and the nonlocal spectrum Nf = -u(k)/kbar (the other two axes
-//      were inverted by the preceding passes), accumulating in FP64 registers
-//      sum_ij h_ij^2 and h22 = (u - <u>) - h00 - h11 (the trace identity:
+//      were inverted by the preceding passes), accumulating in registers (float64;
+//      float32 in the float32 form) sum_ij h_ij^2 and h22 = (u - <u>) - h00 - h11 (the trace identity:
 //      h00 + h11 + h22 = u - <u>, exact on the mesh, saves a sixth transform);
 //   2. evaluates, per point, the residual R of Eq. FullDGP2, B' of Eq. Bwpara,
 //      the discriminant of Eq. nabla^2Cwpara and its + root in the stable form
