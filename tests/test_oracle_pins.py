@@ -475,18 +475,108 @@ def test_plane_wave_potentials_closed_form():
         assert np.max(np.abs(g[1:])) < 1e-12 * np.max(np.abs(want))
 
 
-def test_kick_drift_closed_form():
+def _exact_trajectory(x0, p0, g, s0, s1, omega_m0):
+    """x(s1), p(s1) of dp/dln a = g / E(a), dx/dln a = p / (a^2 E(a)) (Sec. III A equations of motion
+    in ln a with p = a^2 dx/dt, H0 = 1) from (x0, p0) at s0 = ln a0: an adaptive high-order ODE
+    integration, independent of any leapfrog."""
+    from scipy.integrate import solve_ivp
+
+    def rhs(s, y):
+        a = math.exp(s)
+        e = cos.hubble_E(omega_m0, a)
+        return [y[1] / (a * a * e), g / e]
+
+    sol = solve_ivp(rhs, (s0, s1), [x0, p0], method="DOP853", rtol=1e-13, atol=1e-15)
+    return sol.y[0, -1], sol.y[1, -1]
+
+
+def _leapfrog_error(dlna, n_steps, a0=0.5, x0=10.0, p0=3.0, g=-40.0):
+    """Global position error of n_steps oracle kick-drift steps against the exact trajectory.
+    The leapfrog holds momenta at half steps: it starts from the exact p at ln a0 - dlna/2."""
+    s0 = math.log(a0)
+    _, p_half = _exact_trajectory(x0, p0, g, s0, s0 - 0.5 * dlna, OM0)
+    box = 1e9   # no wrap
+    x = np.array([[x0]])
+    v = np.array([[p_half]])
+    f = np.array([[g]])
+    for k in range(n_steps):
+        x, v = pm.kick_drift(x, v, f, a0 * math.exp(k * dlna), dlna, OM0, box)
+    x_exact, _ = _exact_trajectory(x0, p0, g, s0, s0 + n_steps * dlna, OM0)
+    return abs(float(x[0, 0]) - x_exact)
+
+
+def test_kick_drift_is_a_second_order_leapfrog():
+    """Sec. III A: the time integration is a second-order leapfrog.  With a constant force the
+    equations of motion in ln a have an exact solution (integrated independently); over a fixed
+    interval the oracle's global position error must fall 4x each time the step halves (a scheme
+    evaluating the drift or the kick at the wrong time is first order and falls only 2x)."""
+    span = 0.4
+    errs = [_leapfrog_error(span / k, k) for k in (8, 16, 32)]
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 3.6 < coarse / fine < 4.4, errs
+    assert errs[-1] < 1e-3
+
+
+def test_kick_drift_wraps_into_box():
+    """Positions leave the step in [0, L): the same step on a box 32 times larger, reduced modulo L."""
     box, a, dlna = 100.0, 0.5, 0.005
     pos = np.array([[99.99], [10.0], [0.001]])
     vel = np.array([[3.0], [-2.0], [-5.0]])
     force = np.array([[100.0], [0.0], [-40.0]])
     x, v = pm.kick_drift(pos, vel, force, a, dlna, OM0, box)
-    e_n = cos.hubble_E(OM0, a)
-    ah = a * math.exp(dlna / 2)
-    eh = cos.hubble_E(OM0, ah)
-    vv = vel + dlna * force / e_n
-    xx = (pos + dlna * vv / (ah * ah * eh)) % box
-    assert np.allclose(v, vv, rtol=0, atol=1e-14) and np.allclose(x, xx, rtol=0, atol=1e-12)
+    xu, vu = pm.kick_drift(pos, vel, force, a, dlna, OM0, 32 * box)
+    assert np.array_equal(v, vu)
+    assert np.all((x >= 0) & (x < box))
+    assert np.allclose(x, np.mod(xu, box), rtol=0, atol=1e-11)
+    assert x[0, 0] < 1.0 and x[2, 0] > 99.0     # both wrapped
+
+
+def _plane_wave_u(n, box, m, amp):
+    x = np.arange(n) * box / n
+    ph = 2 * np.pi * (m[0] * x[:, None, None] + m[1] * x[None, :, None] + m[2] * x[None, None, :]) / box
+    return amp * np.cos(ph)
+
+
+def test_c_from_u_plane_wave_closed_form():
+    """C = lapbar^{-1} u (Sec. III B: u(k) = -kbar^2 C(k), kbar = kappa |k|).  For a plane wave
+    u = A cos(k0.x) on a diagonal mode, C = -A cos(k0.x) / (kappa |k0|)^2."""
+    n, box = 16, 48.0
+    prm = params()
+    for m in ((1, 2, 3), (-2, 0, 5), (7, 7, 1)):
+        amp = 0.37
+        u = _plane_wave_u(n, box, m, amp)
+        k0sq = (2 * np.pi / box) ** 2 * (m[0] ** 2 + m[1] ** 2 + m[2] ** 2)
+        want = -u / (prm.kappa ** 2 * k0sq)
+        got = fld.c_from_u(u, box, prm)
+        assert np.max(np.abs(got - want)) < 1e-12 * np.max(np.abs(want))
+    # a mean offset has no k = 0 inverse: it is dropped
+    assert np.max(np.abs(fld.c_from_u(np.full((n, n, n), 2.5), box, prm))) < 1e-14
+
+
+def test_delta_gradc_plane_wave_closed_form():
+    """Eq. DGradC: Delta_gradC = 4 pi k^5 P_C(k).  For u = A cos(k0.x) every bin is empty except the
+    one holding |m0|^2, where P_C = L^3 (A / (kappa k0)^2)^2 / (2 N_b) (the two modes +-k0 of a
+    cosine, N_b the bin's mode count from brute-force counting); the bin centre is
+    kf (N/2)^((b + 1/2)/nbins)."""
+    n, box, nb = 16, 100.0, 64
+    prm = params()
+    m = (2, 1, 0)
+    amp = 0.8
+    u = _plane_wave_u(n, box, m, amp)
+    kf = 2 * np.pi / box
+    msq = m[0] ** 2 + m[1] ** 2 + m[2] ** 2
+    f = np.fft.fftfreq(n, 1.0 / n)
+    all_msq = (f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2).ravel()
+    t = [math.ceil((n / 2) ** (2 * b / nb)) for b in range(nb + 1)]
+    t[nb] = (n // 2) ** 2 + 1
+    b0 = max(b for b in range(nb) if t[b] <= msq)
+    count = int(np.sum((all_msq >= t[b0]) & (all_msq < t[b0 + 1])))
+    c_amp = amp / (prm.kappa ** 2 * kf ** 2 * msq)
+    p_c = box ** 3 * c_amp ** 2 / (2 * count)
+    kc = kf * (n / 2) ** ((b0 + 0.5) / nb)
+    got = diagnostics.delta_gradc(u, box, prm, nb)
+    assert abs(got[b0] - 4 * np.pi * kc ** 5 * p_c) < 1e-11 * got[b0]
+    assert np.max(np.abs(np.delete(got, b0))) < 1e-12 * got[b0]
 
 
 def test_power_spectrum_plane_wave_and_counts():
