@@ -16,7 +16,7 @@ Readings of points the paper leaves open (each is applied identically by the
 GPU path):
 * residual norm: r = <|R|> / eps with eps of Eq. normres (the plain average <R>
   vanishes identically on a periodic mesh, so the absolute value is taken, as
-  in eps itself);
+  in eps itself); for eps = 0 (uniform delta) r is 0 when R = 0, else +inf;
 * R uses the full pointwise iterate u (no re-projection of its mean);
 * delta's sample mean is removed first; k = 0 multipliers are 0;
 * the root of Eq. nabla^2Cwpara is evaluated in the algebraically identical
@@ -148,8 +148,14 @@ def residual_field(u, h, nf, s, prm):
 
 
 def normalized_residual(r_field, eps):
-    """<|R|> / eps (Eq. normres with the absolute-value reading)."""
-    return float(np.mean(np.abs(r_field)) / eps)
+    """<|R|> / eps (Eq. normres with the absolute-value reading).
+
+    eps = 0 only for a uniform delta (S = 0), whose exact solution is u = 0; the ratio is then
+    read as 0 when R vanishes identically and +inf otherwise (the paper does not define it)."""
+    num = float(np.mean(np.abs(r_field)))
+    if eps == 0.0:
+        return 0.0 if num == 0.0 else float("inf")
+    return num / eps
 
 
 def picard_update(u, h, nf, s, prm):

@@ -205,6 +205,17 @@ def test_planar_wave_closed_form():
                 assert info.iters == 0
 
 
+def test_uniform_density_has_the_zero_solution():
+    """delta = const (a perfect lattice deposits exactly this): S = 0, eps = 0, and u = 0 solves
+    Eq. FullDGP2 exactly, so the solve returns it after zero updates with r = 0."""
+    n, box = 8, 16.0
+    prm = params(tol=1e-12, lam=3.0)
+    for init in (fld.INIT_LINEAR, fld.INIT_ZERO):
+        u, info = fld.solve(np.full((n, n, n), 0.25), box, prm.with_(init=init))
+        assert info.status == fld.STATUS_OK and info.iters == 0 and info.eps == 0.0 and info.resid == 0.0
+        assert np.all(u == 0.0)
+
+
 def test_first_w13_update_is_spherical_poisson():
     """One w = 1/3 update from u = 0, nonlocal terms off: inserting u_1 into Eq. FullDGP1
     gives the modified Poisson source of Eq. SphPoi (spherical approximation)."""
