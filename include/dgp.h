@@ -122,19 +122,24 @@ size_t dgp_plan_device_bytes(const dgp_plan* plan);
  * grid_fixed [N^3] int64 (optional, may be NULL): sum over particles of
  *   rint(W * 2^40) with W = (w_x w_y) w_z, per-axis weights (1 - f, f) in float64;
  *   identical bits for any particle order.
- * delta [N^3] float64 (optional): Q 2^-40 N^3/np - 1 with its mean removed. */
+ * delta [N^3] float64 (optional): Q 2^-40 N^3/np - 1 with its mean removed.
+ * Positions must be finite; the call does not synchronise, so a non-finite coordinate is not
+ * reported here: it makes every cell of delta NaN (grid_fixed is then unspecified), which a
+ * following dgp_solve_field rejects with DGP_E_INVALID. */
 int dgp_deposit(dgp_plan* plan, const void* pos, int pos_is_fp32, long long np, long long* grid_fixed,
                 double* delta, void* stream);
 
 /* Field solve of Eq. FullDGP2 by FFT-relaxation (Sec. III B, Eq. FFTrelax; w-split of
  * Sec. III C, Eqs. nabla^2Cwpara and Bwpara).
  * delta   [batch][N^3] float64 density contrast (its mean is ignored: k = 0 multipliers are 0).
+ *         A uniform delta has S = 0 and eps = 0: its solution u = 0 is returned with r = 0.
  * u_state [batch][N^3] float64, u = lapbar C.  Read as the starting iterate when
  *         p->init == DGP_INIT_WARM (warm start from the previous step, Sec. III B);
  *         always overwritten with the returned iterate.
  * c_out   [batch][N^3] float64, optional: C = lapbar^{-1} u (C(k) = -u(k)/kbar^2).
  * info    host array of batch dgp_info, optional.
- * Returns the worst status over the batch. */
+ * Returns the worst status over the batch.  DGP_E_INVALID (no output valid) when an element's
+ * delta or warm-start field is not finite (its info status is DGP_E_INVALID too). */
 int dgp_solve_field(dgp_plan* plan, const dgp_params* p, const double* delta, double* u_state, double* c_out,
                     dgp_info* info, void* stream);
 
@@ -151,7 +156,8 @@ int dgp_pm_forces(dgp_plan* plan, const dgp_params* p, const double* delta, cons
  * p->init says), forces, CIC interpolation and a leapfrog step in ln a:
  *   vel += dlna * g / E(a);  pos += dlna * vel / (a_h^2 E(a_h)), a_h = a e^{dlna/2};
  * positions wrapped into [0, L).  vel holds p = a^2 dx/dt at half steps.
- * pos, vel [3][np] (float32 if is_fp32), updated in place. */
+ * pos, vel [3][np] (float32 if is_fp32), updated in place.
+ * DGP_E_INVALID (outputs not valid) when a position is not finite. */
 int dgp_step(dgp_plan* plan, const dgp_params* p, void* pos, void* vel, int is_fp32, long long np, double dlna,
              double* u_state, dgp_info* info, void* stream);
 
@@ -159,7 +165,11 @@ int dgp_step(dgp_plan* plan, const dgp_params* p, void* pos, void* vel, int is_f
  * dgp_solve_field with the same delta and params), solves J^T mu = g by the transposed
  * relaxation and returns dL/ddelta = S^T mu, S = A (1 - beta/kbar) (k = 0 -> 0).
  * delta, u_star, grad_u, grad_delta: [batch][N^3] float64.  Uses p->tol as the relative
- * tolerance on <|J^T mu - g|>/<|g|> and p->max_iter. */
+ * tolerance on <|J^T mu - g|>/<|g|> and p->max_iter; at max_iter the minimum-residual mu is
+ * used and DGP_NOT_CONVERGED returned.  DGP_E_INVALID when u_star has points with
+ * D = 2 (1-w) lam u + alpha <= 0 (the vertex value of a bad point: the solve did not converge
+ * there and the transposed relaxation would divide by zero) or non-finite values, or when
+ * grad_u is not finite.  Synchronises once per transposed-relaxation iteration. */
 int dgp_solve_field_backward(dgp_plan* plan, const dgp_params* p, const double* delta, const double* u_star,
                              const double* grad_u, double* grad_delta, dgp_info* info, void* stream);
 
@@ -167,6 +177,25 @@ int dgp_solve_field_backward(dgp_plan* plan, const dgp_params* p, const double* 
  * grad_pos [3][np] = (N^3/np) sum_c grad_delta[c] dW_c/dx.  Batch-1 plans only. */
 int dgp_deposit_backward(dgp_plan* plan, const void* pos, int pos_is_fp32, long long np, const double* grad_delta,
                          double* grad_pos, void* stream);
+
+/* CIC interpolation of a caller mesh to particles (Sec. III A: the force is interpolated with
+ * the assignment function of the deposit, Eq. CIC): out[m][p] = sum_c W_c(x_p) mesh[m][c],
+ * W_c = w_x w_y w_z with per-axis weights (1 - f, f).  mesh [ncomp][N^3] float64, ncomp in [1, 3];
+ * pos [3][np] (float32 if pos_is_fp32); out [ncomp][np] float64.  Batch-1 plans; asynchronous. */
+int dgp_interp(dgp_plan* plan, const double* mesh, int ncomp, const void* pos, int pos_is_fp32, long long np,
+               double* out, void* stream);
+
+/* Adjoint of dgp_interp for grad_out = dL/dout [ncomp][np] (float64):
+ * grad_pos [3][np] (optional): dL/dx_p = sum_m grad_out[m][p] sum_c mesh[m][c] dW_c/dx_p, with
+ *   dw/dx = -N/L for the lower node and +N/L for the upper one (mesh is required for it);
+ * grad_mesh [ncomp][N^3] (optional): dL/dmesh[m][c] = sum_p grad_out[m][p] W_c(x_p), the transposed
+ *   scatter, summed in 64-bit fixed point (terms rounded to a multiple of 2^-e, e set per call from
+ *   max|grad_out| and the largest cell mass so no sum overflows): the same bits in any particle order.
+ * Uses the plan's deposit workspace (its int64 grid is overwritten).  Asynchronous; a non-finite
+ * position or grad_out value makes grad_mesh NaN.  DGP_E_INVALID when both outputs are NULL or
+ * grad_pos is requested without mesh. */
+int dgp_interp_backward(dgp_plan* plan, const double* mesh, int ncomp, const void* pos, int pos_is_fp32,
+                        long long np, const double* grad_out, double* grad_pos, double* grad_mesh, void* stream);
 
 /* Binned power spectrum of a mesh field ([batch][N^3]), or, with of_c = 1, of
  * C = lapbar^{-1} u for a field u.  nbins logarithmic bins between 2 pi/L and the

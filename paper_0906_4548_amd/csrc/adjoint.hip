@@ -19,14 +19,37 @@
 
 namespace dgp {
 
-// mu = g / D
+// mu = g / D; per workgroup, the number of points where D = 2 (1-w) lam u + alpha is not positive
+// (the vertex value of a bad point gives D = 0: there the implicit adjoint does not exist) or not
+// finite, and the number of non-finite g (part[b][group][0..1])
 __global__ void __launch_bounds__(256)
 k_adj_init(size_t n3, const double* __restrict__ g, const double* __restrict__ u, double* __restrict__ mu,
-           double dscale, double alpha) {
+           double dscale, double alpha, double* __restrict__ part) {
   const int b = blockIdx.y;
   const size_t off = (size_t)b * n3;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256)
-    mu[off + i] = g[off + i] / (dscale * u[off + i] + alpha);
+  double nd = 0.0, ng = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+    const double d = dscale * u[off + i] + alpha;
+    const double gg = g[off + i];
+    nd += (d > 0.0 && isfinite(d)) ? 0.0 : 1.0;
+    ng += isfinite(gg) ? 0.0 : 1.0;
+    mu[off + i] = gg / d;
+  }
+  __shared__ double r0[256], r1[256];
+  r0[threadIdx.x] = nd;
+  r1[threadIdx.x] = ng;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      r0[threadIdx.x] += r0[threadIdx.x + st];
+      r1[threadIdx.x] += r1[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2] = r0[0];
+    part[((size_t)b * gridDim.x + blockIdx.x) * 2 + 1] = r1[0];
+  }
 }
 
 // products p_f = (h00-h22) mu, (h11-h22) mu, h01 mu, h02 mu, h12 mu, mu; partial sums of h22 mu
@@ -157,8 +180,8 @@ void launch_nonelliptic(size_t n3, int batch, const double* u, const double* h5,
 }
 
 void launch_adj_init(size_t n3, int batch, const double* g, const double* u, double* mu, double dscale, double alpha,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_init, dim3(adj_groups(n3), batch), dim3(256), 0, s, n3, g, u, mu, dscale, alpha);
+                     double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_init, dim3(adj_groups(n3), batch), dim3(256), 0, s, n3, g, u, mu, dscale, alpha, part);
 }
 
 void launch_adj_products(size_t n3, int batch, const double* mu, const double* u, const double* h5,

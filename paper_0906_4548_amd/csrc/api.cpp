@@ -214,6 +214,11 @@ struct dgp_plan {
   // adjoint (allocated on first use)
   double* adj = nullptr;             // [15][B][n3]
   double* adj_red = nullptr;
+  // non-finite particle flag (device, one 8-byte slot) and its pinned host copy; fixed-point
+  // scale state of the interpolation adjoint
+  int* flag = nullptr;
+  int* flag_host = nullptr;
+  unsigned long long* fx_state = nullptr;
   std::vector<void*> dev_allocs;
   std::vector<void*> host_allocs;
   size_t bytes = 0;
@@ -353,6 +358,9 @@ static int plan_alloc(dgp_plan* pl) {
     else
       TRY(dalloc(pl, &pl->mesh3, 3 * n3));
   }
+  TRY(dalloc(pl, &pl->flag, 2));
+  TRY(halloc(pl, &pl->flag_host, 2));
+  TRY(dalloc(pl, &pl->fx_state, 4));
   TRY(dalloc(pl, &pl->bin_tab, 129 + 128 * B));
   TRY(dalloc(pl, &pl->bin_partial, (size_t)p3_row_groups(pl->n) * B * 2 * 128));
   TRY(halloc(pl, &pl->bin_host, (size_t)p3_row_groups(pl->n) * B * 2 * 128));
@@ -572,12 +580,16 @@ static int collect_enqueue(dgp_plan* pl, Ws<T>& w, double* u_state, hipStream_t 
 
 // After the stream is synchronised: fill info and return the worst status.
 static int collect_finish(dgp_plan* pl, dgp_info* info, float ms) {
-  int worst = DGP_OK;
+  int worst = DGP_OK, invalid = -1;
   for (int b = 0; b < pl->batch; ++b) {
     const SolveCtl& C = pl->ctl_host[b];
-    if (status_rank(C.status) > status_rank(worst)) worst = C.status;
+    if (C.status == kStatusInvalid) {
+      if (invalid < 0) invalid = b;
+    } else if (status_rank(C.status) > status_rank(worst)) {
+      worst = C.status;
+    }
     if (!info) continue;
-    info[b].status = C.status;
+    info[b].status = C.status == kStatusInvalid ? DGP_E_INVALID : C.status;
     info[b].iters = C.iters1 + C.iters;
     info[b].passes = C.passes1 + C.passes;
     info[b].passes_fp64 = C.passes;
@@ -588,6 +600,9 @@ static int collect_finish(dgp_plan* pl, dgp_info* info, float ms) {
     info[b].mean_u = pl->means_host[b];
     info[b].ms_total = ms;
   }
+  if (invalid >= 0)
+    return fail(DGP_E_INVALID, "batch element %d: non-finite input or iterate (delta, particle positions or the "
+                "warm-start field); no output is valid", invalid);
   return worst;
 }
 
@@ -612,7 +627,7 @@ static int solve64(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
   if (p->init == DGP_INIT_WARM) {
     HIPCHK(hipMemcpyAsync(w.U, u_state, sizeof(double) * B * pl->n3, hipMemcpyDeviceToDevice, s));
   } else if (p->init == DGP_INIT_ZERO) {
-    HIPCHK(hipMemsetAsync(w.U, 0, sizeof(double) * B * pl->n3, s));
+    launch_fill_zero(w.U, (size_t)B * pl->n3, s);
   }
   launch_absmean<double>(pl->n3, w.S, B, pl->red, pl->vec, nullptr, s);
   launch_ctl_init(pl->ctl, pl->vec, B, s);
@@ -688,8 +703,8 @@ int solve32_polish(dgp_plan* pl, const dgp_params* p, const double* delta, doubl
     HIPCHK(hipMemcpyAsync(w.U, u_state, sizeof(double) * B * n3, hipMemcpyDeviceToDevice, s));
     launch_convert<float>(B * n3, u_state, 0, w32.U, s);
   } else if (p->init == DGP_INIT_ZERO) {
-    HIPCHK(hipMemsetAsync(w.U, 0, sizeof(double) * B * n3, s));
-    HIPCHK(hipMemsetAsync(w32.U, 0, sizeof(float) * B * n3, s));
+    launch_fill_zero(w.U, (size_t)B * n3, s);
+    launch_fill_zero(w32.U, (size_t)B * n3 / 2, s);   // n3 is even
   }
   // eps = <|S|> of the float64 source; it stays in the control blocks for both phases
   launch_absmean<double>(n3, w.S, B, pl->red, pl->vec, nullptr, s);
@@ -726,13 +741,16 @@ static int require_batch1(const dgp_plan* pl) {
   return DGP_OK;
 }
 
+// (a non-finite position raises the plan's flag and turns delta into NaN, which the solve's
+// source then reports as invalid input)
 static int deposit_impl(dgp_plan* pl, const void* pos, int fp32, long long np, long long* grid, double* delta,
                         bool remove_mean, hipStream_t s) {
   Timed tm(pl, s, DGP_T_DEPOSIT);
-  HIPCHK(hipMemsetAsync(grid, 0, sizeof(long long) * pl->n3, s));
-  launch_deposit(pl->n, pl->box, pos, fp32, np, grid, s);
+  launch_fill_zero(grid, pl->n3, s);
+  launch_zero_flag(pl->flag, s);
+  launch_deposit(pl->n, pl->box, pos, fp32, np, grid, pl->flag, s);
   if (delta) {
-    launch_counts_to_delta(pl->n, grid, np, delta, s);
+    launch_counts_to_delta(pl->n, grid, np, delta, pl->flag, s);
     if (remove_mean) {
       launch_absmean<double>(pl->n3, delta, 1, pl->red, nullptr, pl->vec, s);
       launch_sub_mean(pl->n3, delta, 1, pl->vec, s);
@@ -823,7 +841,7 @@ extern "C" int dgp_pm_forces(dgp_plan* pl, const dgp_params* p, const double* de
   TRY(force_mesh(pl, p, delta, u_state, phi_n, false, s));
   int mfp32 = 0;
   const void* mesh = mesh_of(pl, &mfp32);
-  launch_interp(pl->n, pl->box, mesh, mfp32, pos, pos_is_fp32, np, force, s);
+  launch_interp(pl->n, pl->box, mesh, mfp32, 3, pos, pos_is_fp32, np, force, s);
   LAUNCHCHK();
   return DGP_OK;
 }
@@ -857,12 +875,39 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
     launch_interp_kick_drift(pl->n, pl->box, mesh, mfp32, pos, vel, is_fp32, np, kick, drift, s);
   }
   LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(pl->flag_host, pl->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   timing_flush(pl);
+  if (*pl->flag_host)
+    return fail(DGP_E_INVALID, "non-finite particle position: the step's outputs are not valid");
   if (!solve) return DGP_OK;
   float ms = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, pl->ev0, pl->ev1));
   return collect_finish(pl, info, ms);
+}
+
+extern "C" int dgp_interp(dgp_plan* pl, const double* mesh, int ncomp, const void* pos, int pos_is_fp32, long long np,
+                          double* out, void* stream) {
+  if (!pl || !mesh || !pos || !out || np < 1) return fail(DGP_E_INVALID, "plan, mesh, pos, out and np >= 1 are required");
+  if (ncomp < 1 || ncomp > 3) return fail(DGP_E_INVALID, "ncomp must be in [1, 3]");
+  TRY(require_batch1(pl));
+  launch_interp(pl->n, pl->box, mesh, 0, ncomp, pos, pos_is_fp32, np, out, static_cast<hipStream_t>(stream));
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
+extern "C" int dgp_interp_backward(dgp_plan* pl, const double* mesh, int ncomp, const void* pos, int pos_is_fp32,
+                                   long long np, const double* grad_out, double* grad_pos, double* grad_mesh,
+                                   void* stream) {
+  if (!pl || !pos || !grad_out || np < 1) return fail(DGP_E_INVALID, "plan, pos, grad_out and np >= 1 are required");
+  if (ncomp < 1 || ncomp > 3) return fail(DGP_E_INVALID, "ncomp must be in [1, 3]");
+  if (!grad_pos && !grad_mesh) return fail(DGP_E_INVALID, "nothing to compute: grad_pos and grad_mesh are both NULL");
+  if (grad_pos && !mesh) return fail(DGP_E_INVALID, "grad_pos needs the mesh");
+  TRY(require_batch1(pl));
+  launch_interp_backward(pl->n, pl->box, mesh, ncomp, pos, pos_is_fp32, np, grad_out, grad_pos, grad_mesh, pl->grid,
+                         pl->fx_state, pl->flag, static_cast<hipStream_t>(stream));
+  LAUNCHCHK();
+  return DGP_OK;
 }
 
 extern "C" int dgp_deposit_backward(dgp_plan* pl, const void* pos, int pos_is_fp32, long long np,
@@ -1065,10 +1110,20 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   const int G = adjoint_groups(n3);
   // Hessians of u* (h00, h11, h01, h02, h12) and <u*>
   TRY(hessians(pl, p, u_star, H5, s));
-  launch_adj_init(n3, B, grad_u, u_star, MU, 2.0 * (1.0 - w) * lam, alpha, s);
+  launch_adj_init(n3, B, grad_u, u_star, MU, 2.0 * (1.0 - w) * lam, alpha, pl->adj_red, s);
+  launch_pair_means(pl->adj_red, G, n3, B, pl->vec, pl->vec + B, s);
   LAUNCHCHK();
+  std::vector<double> host(2 * B);
+  HIPCHK(hipMemcpyAsync(host.data(), pl->vec, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int b = 0; b < B; ++b) {
+    if (host[b] > 0.0)
+      return fail(DGP_E_INVALID, "batch element %d: u* has points where 2 (1-w) lam u + alpha <= 0 (bad-point "
+                  "vertices of an unconverged solve) or non-finite values; the implicit adjoint does not exist there", b);
+    if (host[B + b] > 0.0) return fail(DGP_E_INVALID, "batch element %d: grad_u is not finite", b);
+  }
   std::vector<int> done(B, 0), iters(B, 0);
-  std::vector<double> resid(B, 0.0), rmin(B, 1e300), host(2 * B);
+  std::vector<double> resid(B, 0.0), rmin(B, 1e300);
   int it = 0;
   for (;; ++it) {
     launch_adj_products(n3, B, MU, u_star, H5, pl->mean_u, P6, pl->adj_red, s);
@@ -1084,17 +1139,22 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
     LAUNCHCHK();
     HIPCHK(hipMemcpyAsync(host.data(), pl->vec + B, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    // RES keeps, per element, the minimum-residual mu seen (returned if max_iter is reached) or
+    // the converged one
     int active = 0;
     for (int b = 0; b < B; ++b) {
       if (done[b]) continue;
       const double r = host[B + b] > 0.0 ? host[b] / host[B + b] : 0.0;
       resid[b] = r;
-      rmin[b] = std::min(rmin[b], r);
-      if (r <= p->tol || it >= p->max_iter) {
-        done[b] = (r <= p->tol) ? 1 : 2;
-        iters[b] = it;
+      const bool conv = r <= p->tol;
+      if (conv || r < rmin[b])
         HIPCHK(hipMemcpyAsync(RES + (size_t)b * n3, MU + (size_t)b * n3, sizeof(double) * n3,
                               hipMemcpyDeviceToDevice, s));
+      rmin[b] = std::min(rmin[b], r);
+      if (conv || it >= p->max_iter || r != r) {
+        done[b] = conv ? 1 : 2;
+        iters[b] = it;
+        if (!conv) resid[b] = rmin[b];
       } else {
         ++active;
       }

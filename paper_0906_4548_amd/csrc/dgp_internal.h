@@ -45,9 +45,11 @@ struct SpecCoef {
 
 // Per-batch-element control block of the relaxation (device memory).
 constexpr int kMaxHist = 256;
+constexpr int kStatusInvalid = 3;
 struct SolveCtl {
   int done;         // 1 once the returned iterate is decided
-  int status;       // 0 ok, 1 not converged (max_iter), 2 stopped at min residual with bad points
+  int status;       // 0 ok, 1 not converged (max_iter), 2 stopped at min residual with bad points,
+                    // kStatusInvalid: non-finite input or iterate (no valid output)
   int iters;        // updates applied to the current iterate
   int cur;          // buffer index holding u^(iters)
   int out;          // buffer the next update writes
@@ -189,8 +191,10 @@ void launch_pair_means(const double* part, int groups, size_t n3, int batch, dou
 
 // adjoint (transposed relaxation) pointwise kernels
 int adjoint_groups(size_t n3);
+// mu = g / D, with per-workgroup counts of points where D <= 0 (or not finite) and of non-finite g
+// in part (adjoint_groups(n3) x batch x 2 doubles)
 void launch_adj_init(size_t n3, int batch, const double* g, const double* u, double* mu, double dscale, double alpha,
-                     hipStream_t s);
+                     double* part, hipStream_t s);
 void launch_adj_products(size_t n3, int batch, const double* mu, const double* u, const double* h5,
                          const double* mean_u, double* p6, double* part, hipStream_t s);
 void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, double* mu_new, const double* u,
@@ -202,18 +206,28 @@ void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, 
 void launch_nonelliptic(size_t n3, int batch, const double* u, const double* h5, const double* mean_u, double lam,
                         double alpha, double* part, hipStream_t s);
 
-// PM kernels
-void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid,
+// PM kernels.  `bad` (device int) is raised when a particle coordinate is not finite.
+void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid, int* bad,
                     hipStream_t s);
-void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s);
+// delta = Q 2^-40 N^3/np - 1 (NaN everywhere when *bad is set)
+void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s);
 void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
-// mesh3: [3][n3] float64 (mesh_fp32 = 0) or float32 (1)
-void launch_interp(int n, double box, const void* mesh3, int mesh_fp32, const void* pos, int pos_fp32, long long np,
-                   double* force, hipStream_t s);
+// zero `words` 8-byte words (a fill kernel: no memset node in captured streams)
+void launch_fill_zero(void* p, size_t words, hipStream_t s);
+void launch_zero_flag(int* bad, hipStream_t s);
+// out[k][p] = CIC interpolation of component k of mesh [nc][n3] (nc in 1..3), float64 (mesh_fp32 = 0)
+// or float32 (1) mesh
+void launch_interp(int n, double box, const void* mesh, int mesh_fp32, int nc, const void* pos, int pos_fp32,
+                   long long np, double* out, hipStream_t s);
 void launch_interp_kick_drift(int n, double box, const void* mesh3, int mesh_fp32, void* pos, void* vel, int fp32,
                               long long np, double kick, double drift, hipStream_t s);
 void launch_deposit_backward(int n, double box, const void* pos, int pos_fp32, long long np,
                              const double* grad_delta, double* grad_pos, hipStream_t s);
+// adjoint of launch_interp for dL/dout = g [nc][np]: grad_pos [3][np] (optional) and grad_mesh [nc][n3]
+// (optional, deterministic fixed-point sums); grid: n3 int64 scratch, st: 3 words of scratch
+void launch_interp_backward(int n, double box, const double* mesh, int nc, const void* pos, int pos_fp32, long long np,
+                            const double* g, double* grad_pos, double* grad_mesh, long long* grid,
+                            unsigned long long* st, int* bad, hipStream_t s);
 template <typename T>
 void launch_convert(size_t count, const void* in, int in_fp32, T* out, hipStream_t s);
 

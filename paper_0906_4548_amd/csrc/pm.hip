@@ -46,32 +46,6 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
   return cic_at(s3, n);
 }
 
-template <typename P>
-__global__ void __launch_bounds__(256)
-k_deposit(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
-#pragma clang fp contract(off)
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= np) return;
-  const Cic c = cic_of(pos, np, p, n, scale);
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const double wx = a ? c.w1[0] : c.w0[0];
-    const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
-      const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
-        const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
-        const unsigned long long q = (unsigned long long)(long long)rint(wgt * kQScale);
-        atomicAdd(&grid[(ix * n + iy) * n + iz], q);
-      }
-    }
-  }
-}
-
 // Binned deposit.  A workgroup takes a chunk of consecutive particles, finds the
 // periodic bounding box of their CIC cells and, when the box fits the LDS histogram,
 // sums the chunk's quantised weights there with LDS atomics and then adds each
@@ -173,6 +147,18 @@ __device__ __forceinline__ void load_chunk(const P* __restrict__ a, long long np
   }
 }
 
+// raise *bad when one of the thread's particles has a non-finite coordinate (the cell index of
+// such a particle is still reduced into the mesh, so no access leaves it; the caller reports it)
+template <int PPT, typename P>
+__device__ __forceinline__ void flag_nonfinite(const P (&xs)[PPT][3], int* __restrict__ bad) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ok = ok && isfinite(double(xs[k][d]));
+  if (!ok) atomicOr(bad, 1);
+}
+
 // mesh index of box cell i (row-major over the box extents), wrapped onto the periodic mesh
 __device__ __forceinline__ size_t box_cell(int i, const Cic& cr, const int (&bx)[6], int n) {
   const int plane = bx[4] * bx[5];
@@ -186,12 +172,14 @@ __device__ __forceinline__ size_t box_cell(int i, const Cic& cr, const int (&bx)
 
 template <typename P>
 __global__ void __launch_bounds__(256)
-k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid) {
+k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid,
+              int* __restrict__ bad) {
 #pragma clang fp contract(off)
   __shared__ unsigned long long hist[kBinCap];
   const long long p0 = xcd_chunk() * kDepChunk;
   P xs[kDepPPT][3];
   load_chunk<kDepPPT>(pos, np, p0, xs);
+  flag_nonfinite<kDepPPT>(xs, bad);
   Cic cr, cs[kDepPPT];
   int off[kDepPPT][3], bx[6];
   const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, kBinCap, cr, cs, off, bx);
@@ -236,11 +224,13 @@ k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsi
 }
 
 __global__ void __launch_bounds__(256)
-k_counts_to_delta(const long long* __restrict__ grid, size_t n3, double qscale, double* __restrict__ delta) {
+k_counts_to_delta(const long long* __restrict__ grid, size_t n3, double qscale, double* __restrict__ delta,
+                  const int* __restrict__ bad) {
 #pragma clang fp contract(off)
+  const bool nan_out = *bad != 0;   // a non-finite position: delta is undefined, mark it so
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
     const double d = double(grid[i]) * qscale;
-    delta[i] = d - 1.0;
+    delta[i] = nan_out ? __builtin_nan("") : d - 1.0;
   }
 }
 
@@ -252,12 +242,13 @@ k_sub_mean(double* __restrict__ x, size_t n3, const double* __restrict__ mean) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) xb[i] -= m;
 }
 
-// CIC interpolation of a 3-component field: f[k] = sum over the 8 corners of
+// CIC interpolation of an NC-component field: f[k] = sum over the 8 corners of
 // (w_x w_y) w_z times the corner value of component k; `at(a, b, c, k)` reads the value.
-template <class At>
-__device__ __forceinline__ void gather_corners(const Cic& c, const At& at, double (&f)[3]) {
+template <int NC, class At>
+__device__ __forceinline__ void gather_corners(const Cic& c, const At& at, double (&f)[NC]) {
 #pragma clang fp contract(off)
-  f[0] = f[1] = f[2] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) f[k] = 0.0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const double wx = a ? c.w1[0] : c.w0[0];
@@ -267,70 +258,47 @@ __device__ __forceinline__ void gather_corners(const Cic& c, const At& at, doubl
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc) {
         const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
-        f[0] += wgt * at(a, b, cc, 0);
-        f[1] += wgt * at(a, b, cc, 1);
-        f[2] += wgt * at(a, b, cc, 2);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) f[k] += wgt * at(a, b, cc, k);
       }
     }
   }
 }
 
-// interpolate a 3-component mesh [3][N^3] to particles
-template <typename M>
-__device__ __forceinline__ void gather3(const M* __restrict__ mesh3, size_t n3, int n, const Cic& c,
-                                        double (&f)[3]) {
-  gather_corners(
-      c,
-      [&](int a, int b, int cc, int k) {
-        const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
-        const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
-        const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
-        return double(mesh3[(size_t)k * n3 + (ix * n + iy) * n + iz]);
-      },
-      f);
+// flat mesh index of corner (a, b, cc) of a particle's CIC cell
+__device__ __forceinline__ size_t corner_index(const Cic& c, int a, int b, int cc, int n) {
+  const size_t ix = (size_t)(a ? c.i1[0] : c.i0[0]);
+  const size_t iy = (size_t)(b ? c.i1[1] : c.i0[1]);
+  const size_t iz = (size_t)(cc ? c.i1[2] : c.i0[2]);
+  return (ix * n + iy) * n + iz;
 }
 
-template <typename P, typename M>
+// interpolate an NC-component mesh [NC][N^3] to particles
+template <int NC, typename M>
+__device__ __forceinline__ void gather_mesh(const M* __restrict__ mesh, size_t n3, int n, const Cic& c,
+                                            double (&f)[NC]) {
+  gather_corners<NC>(
+      c, [&](int a, int b, int cc, int k) { return double(mesh[(size_t)k * n3 + corner_index(c, a, b, cc, n)]); }, f);
+}
+
+// out[k][p] = sum_c W_c(x_p) mesh[k][c]
+template <typename P, typename M, int NC>
 __global__ void __launch_bounds__(256)
-k_interp(const M* __restrict__ mesh3, const P* __restrict__ pos, long long np, int n, double scale,
-         double* __restrict__ force) {
+k_interp(const M* __restrict__ mesh, const P* __restrict__ pos, long long np, int n, double scale,
+         double* __restrict__ out) {
   const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
   if (p >= np) return;
   const Cic c = cic_of(pos, np, p, n, scale);
-  double f[3];
-  gather3<M>(mesh3, (size_t)n * n * n, n, c, f);
-  force[p] = f[0];
-  force[np + p] = f[1];
-  force[2 * np + p] = f[2];
-}
-
-// leapfrog with momenta at half steps: p += kick * g(x_n); x += drift * p; wrap into [0, L)
-template <typename P, typename M>
-__global__ void __launch_bounds__(256)
-k_interp_kick_drift(const M* __restrict__ mesh3, P* __restrict__ pos, P* __restrict__ vel, long long np,
-                    int n, double scale, double box, double kick, double drift) {
-#pragma clang fp contract(off)
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (p >= np) return;
-  const Cic c = cic_of(pos, np, p, n, scale);
-  double f[3];
-  gather3<M>(mesh3, (size_t)n * n * n, n, c, f);
+  double f[NC];
+  gather_mesh<NC, M>(mesh, (size_t)n * n * n, n, c, f);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const size_t k = (size_t)d * np + p;
-    const double v = double(vel[k]) + kick * f[d];
-    double x = double(pos[k]) + drift * v;
-    x = x - box * floor(x / box);
-    P xo = P(x);
-    if (xo >= P(box)) xo = xo - P(box);
-    vel[k] = P(v);
-    pos[k] = xo;
-  }
+  for (int k = 0; k < NC; ++k) out[(size_t)k * np + p] = f[k];
 }
 
-// Kick-drift with the force mesh of the chunk's box staged in LDS (coalesced rows), the
-// chunking of the binned deposit (smaller chunks: three components per cell in LDS);
-// chunks with larger boxes gather from the mesh.
+// Leapfrog with momenta at half steps: p += kick * g(x_n); x += drift * p; wrap into [0, L).
+// The force mesh of the chunk's box is staged in LDS (coalesced rows), with the chunking of the
+// binned deposit (smaller chunks: three components per cell in LDS); chunks with larger boxes
+// gather from the mesh.
 #ifndef DGP_GATHER_CHUNK
 #define DGP_GATHER_CHUNK 256
 #endif
@@ -373,7 +341,7 @@ k_interp_kick_drift_bin(const M* __restrict__ mesh3, P* __restrict__ pos, P* __r
     if (p >= np) continue;
     double f[3];
     if (binned) {
-      gather_corners(
+      gather_corners<3>(
           cs[k],
           [&](int a, int b, int cc, int q) {
             const int li = ((off[k][0] + a - bx[0]) * bx[4] + (off[k][1] + b - bx[1])) * bx[5] + (off[k][2] + cc - bx[2]);
@@ -381,7 +349,7 @@ k_interp_kick_drift_bin(const M* __restrict__ mesh3, P* __restrict__ pos, P* __r
           },
           f);
     } else {
-      gather3<M>(mesh3, n3, n, cs[k], f);
+      gather_mesh<3, M>(mesh3, n3, n, cs[k], f);
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -432,6 +400,185 @@ k_deposit_backward(const P* __restrict__ pos, long long np, int n, double scale,
   grad[2 * np + p] = gz * mass;
 }
 
+// ------------------------------------------------------------------ CIC interpolation adjoint
+// The interpolation out[m][p] = sum_c W_c(x_p) mesh[m][c] (Sec. III A: forces are interpolated
+// with the deposit's assignment function, Eq. CIC; unquantised weights W_c = w_x w_y w_z) has,
+// for g = dL/dout,
+//   dL/dx_p        = sum_m g[m][p] sum_c mesh[m][c] dW_c/dx_p     (gather, k_interp_grad_pos)
+//   dL/dmesh[m][c] = sum_p g[m][p] W_c(x_p)                       (scatter, k_interp_grad_mesh_bin)
+// The scatter sums in 64-bit fixed point, so the result has the same bits in any particle order:
+// every term is rounded to an integer multiple of 2^-e, e chosen per call so that no sum can
+// reach 2^62 (a cell's sum is at most max|g| times its mass sum_p W_c, which the deposit of the
+// same positions bounds).
+
+// dL/dx_p: per particle, the 8 corners of its cell
+template <typename P, int NC>
+__global__ void __launch_bounds__(256)
+k_interp_grad_pos(const double* __restrict__ mesh, const P* __restrict__ pos, long long np, int n, double scale,
+                  const double* __restrict__ g, double* __restrict__ grad) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= np) return;
+  const Cic c = cic_of(pos, np, p, n, scale);
+  const size_t n3 = (size_t)n * n * n;
+  double gm[NC];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) gm[m] = g[(size_t)m * np + p];
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const double wx = a ? c.w1[0] : c.w0[0];
+    const double dx = a ? scale : -scale;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double wy = b ? c.w1[1] : c.w0[1];
+      const double dy = b ? scale : -scale;
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        const double wz = cc ? c.w1[2] : c.w0[2];
+        const double dz = cc ? scale : -scale;
+        const size_t idx = corner_index(c, a, b, cc, n);
+        double proj = 0.0;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) proj += gm[m] * mesh[(size_t)m * n3 + idx];
+        gx += proj * dx * wy * wz;
+        gy += proj * wx * dy * wz;
+        gz += proj * wx * wy * dz;
+      }
+    }
+  }
+  grad[p] = gx;
+  grad[np + p] = gy;
+  grad[2 * np + p] = gz;
+}
+
+__global__ void k_zero_scale_state(unsigned long long* __restrict__ st, int* __restrict__ bad) {
+  if (threadIdx.x < 3) st[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) *bad = 0;
+}
+
+// st[0]: bit pattern of max |g| (non-negative doubles order like their bit patterns), st[1]: the
+// largest fixed-point mass of the grid; *bad raised for a non-finite g
+__global__ void __launch_bounds__(256)
+k_max_abs_and_mass(const double* __restrict__ g, size_t count, const long long* __restrict__ grid, size_t n3,
+                   unsigned long long* __restrict__ st, int* __restrict__ bad) {
+  double m = 0.0;
+  long long mm = 0;
+  bool ok = true;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+    const double v = g[i];
+    ok = ok && isfinite(v);
+    m = fmax(m, fabs(v));
+  }
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) mm = max(mm, grid[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = fmax(m, __shfl_xor(m, o, 64));
+    mm = max(mm, __shfl_xor(mm, o, 64));
+  }
+  if (!ok) atomicOr(bad, 1);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&st[0], (unsigned long long)__double_as_longlong(m));
+    atomicMax(&st[1], (unsigned long long)mm);
+  }
+}
+
+// st[2] = e with (max|g|) (mass bound) 2^e < 2^62
+__global__ void k_interp_scale(unsigned long long* __restrict__ st) {
+  if (threadIdx.x != 0) return;
+  const double gmax = __longlong_as_double((long long)st[0]);
+  const double mass = double((long long)st[1]) * 0x1p-40 * (1.0 + 0x1p-20) + 0x1p-20;
+  const double bound = gmax * mass;
+  int e = 0;
+  if (bound > 0.0 && isfinite(bound)) {
+    int ex = 0;
+    (void)frexp(bound, &ex);   // bound < 2^ex
+    e = 62 - ex;
+    e = e > 960 ? 960 : (e < -960 ? -960 : e);
+  }
+  st[2] = (unsigned long long)(long long)e;
+}
+
+template <typename P, int NC>
+__global__ void __launch_bounds__(256)
+k_interp_grad_mesh_bin(const P* __restrict__ pos, long long np, int n, double scale, const double* __restrict__ g,
+                       const unsigned long long* __restrict__ st, unsigned long long* __restrict__ acc) {
+#pragma clang fp contract(off)
+  __shared__ unsigned long long hist[NC * kBinCap];
+  const size_t n3 = (size_t)n * n * n;
+  const int e = (int)(long long)st[2];
+  const long long p0 = xcd_chunk() * kDepChunk;
+  P xs[kDepPPT][3];
+  load_chunk<kDepPPT>(pos, np, p0, xs);
+  Cic cr, cs[kDepPPT];
+  int off[kDepPPT][3], bx[6];
+  const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, kBinCap, cr, cs, off, bx);
+  const int vol = bx[3] * bx[4] * bx[5];
+  if (binned)
+    for (int i = threadIdx.x; i < vol; i += 256)
+#pragma unroll
+      for (int m = 0; m < NC; ++m) hist[m * kBinCap + i] = 0ull;
+  lds_barrier();
+#pragma unroll
+  for (int k = 0; k < kDepPPT; ++k) {
+    const long long p = p0 + threadIdx.x + k * 256;
+    if (p >= np) continue;
+    const Cic& c = cs[k];
+    double gm[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) gm[m] = g[(size_t)m * np + p];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const double wx = a ? c.w1[0] : c.w0[0];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const double wxy = wx * (b ? c.w1[1] : c.w0[1]);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+          const double wgt = wxy * (cc ? c.w1[2] : c.w0[2]);
+          const int li = ((off[k][0] + a - bx[0]) * bx[4] + (off[k][1] + b - bx[1])) * bx[5] + (off[k][2] + cc - bx[2]);
+          const size_t gi = corner_index(c, a, b, cc, n);
+#pragma unroll
+          for (int m = 0; m < NC; ++m) {
+            const unsigned long long q = (unsigned long long)(long long)rint(ldexp(gm[m] * wgt, e));
+            if (binned) atomicAdd(&hist[m * kBinCap + li], q);
+            else atomicAdd(&acc[(size_t)m * n3 + gi], q);
+          }
+        }
+      }
+    }
+  }
+  if (!binned) return;
+  lds_barrier();
+  for (int i = threadIdx.x; i < vol; i += 256) {
+    const size_t gi = box_cell(i, cr, bx, n);
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+      const unsigned long long v = hist[m * kBinCap + i];
+      if (v != 0ull) atomicAdd(&acc[(size_t)m * n3 + gi], v);
+    }
+  }
+}
+
+// in place: the fixed-point sums (int64 bit patterns) become doubles q 2^-e (NaN when *bad)
+__global__ void __launch_bounds__(256)
+k_fixed_to_double(unsigned long long* __restrict__ x, size_t count, const unsigned long long* __restrict__ st,
+                  const int* __restrict__ bad) {
+  const int e = (int)(long long)st[2];
+  const bool nan_out = *bad != 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+    const double v = nan_out ? __builtin_nan("") : ldexp(double((long long)x[i]), -e);
+    x[i] = (unsigned long long)__double_as_longlong(v);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(unsigned long long* __restrict__ x, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) x[i] = 0ull;
+}
+
+__global__ void k_zero_flag(int* __restrict__ bad) {
+  if (threadIdx.x == 0) *bad = 0;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_convert(size_t count, const void* __restrict__ in, int in_fp32, T* __restrict__ out) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256)
@@ -447,84 +594,69 @@ static unsigned grid_strided(size_t count) {
   return unsigned(g > 8192 ? 8192 : (g < 1 ? 1 : g));
 }
 
-#ifndef DGP_DEPOSIT_BINNED
-#define DGP_DEPOSIT_BINNED 1
-#endif
-
-void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid, hipStream_t s) {
+void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid, int* bad,
+                    hipStream_t s) {
   const double scale = double(n) / box;
   auto* out = reinterpret_cast<unsigned long long*>(grid);
-  if (DGP_DEPOSIT_BINNED) {
-    const unsigned g = unsigned((np + kDepChunk - 1) / kDepChunk);
-    if (pos_fp32)
-      hipLaunchKernelGGL((k_deposit_bin<float>), dim3(g), dim3(256), 0, s, static_cast<const float*>(pos), np, n,
-                         scale, out);
-    else
-      hipLaunchKernelGGL((k_deposit_bin<double>), dim3(g), dim3(256), 0, s, static_cast<const double*>(pos), np, n,
-                         scale, out);
-  } else if (pos_fp32) {
-    hipLaunchKernelGGL((k_deposit<float>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const float*>(pos), np, n,
-                       scale, out);
-  } else {
-    hipLaunchKernelGGL((k_deposit<double>), dim3(grid_for(np)), dim3(256), 0, s, static_cast<const double*>(pos), np,
-                       n, scale, out);
-  }
+  const unsigned g = unsigned((np + kDepChunk - 1) / kDepChunk);
+  if (pos_fp32)
+    hipLaunchKernelGGL((k_deposit_bin<float>), dim3(g), dim3(256), 0, s, static_cast<const float*>(pos), np, n, scale,
+                       out, bad);
+  else
+    hipLaunchKernelGGL((k_deposit_bin<double>), dim3(g), dim3(256), 0, s, static_cast<const double*>(pos), np, n,
+                       scale, out, bad);
 }
 
-
-void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, hipStream_t s) {
+void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s) {
   const size_t n3 = (size_t)n * n * n;
   const double qscale = ldexp(double(n3) / double(np), -40);
-  hipLaunchKernelGGL(k_counts_to_delta, dim3(grid_strided(n3)), dim3(256), 0, s, grid, n3, qscale, delta);
+  hipLaunchKernelGGL(k_counts_to_delta, dim3(grid_strided(n3)), dim3(256), 0, s, grid, n3, qscale, delta, bad);
+}
+
+void launch_fill_zero(void* p, size_t words, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_zero, dim3(grid_strided(words)), dim3(256), 0, s, static_cast<unsigned long long*>(p),
+                     words);
 }
 
 void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_strided(n3), batch), dim3(256), 0, s, x, n3, mean);
 }
 
-template <typename M>
-static void interp_m(int n, double box, const M* mesh3, const void* pos, int pos_fp32, long long np, double* force,
+template <typename M, int NC>
+static void interp_m(int n, double box, const M* mesh, const void* pos, int pos_fp32, long long np, double* out,
                      hipStream_t s) {
   const double scale = double(n) / box;
   if (pos_fp32)
-    hipLaunchKernelGGL((k_interp<float, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
-                       static_cast<const float*>(pos), np, n, scale, force);
+    hipLaunchKernelGGL((k_interp<float, M, NC>), dim3(grid_for(np)), dim3(256), 0, s, mesh,
+                       static_cast<const float*>(pos), np, n, scale, out);
   else
-    hipLaunchKernelGGL((k_interp<double, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
-                       static_cast<const double*>(pos), np, n, scale, force);
+    hipLaunchKernelGGL((k_interp<double, M, NC>), dim3(grid_for(np)), dim3(256), 0, s, mesh,
+                       static_cast<const double*>(pos), np, n, scale, out);
 }
 
-void launch_interp(int n, double box, const void* mesh3, int mesh_fp32, const void* pos, int pos_fp32, long long np,
-                   double* force, hipStream_t s) {
-  if (mesh_fp32)
-    interp_m(n, box, static_cast<const float*>(mesh3), pos, pos_fp32, np, force, s);
-  else
-    interp_m(n, box, static_cast<const double*>(mesh3), pos, pos_fp32, np, force, s);
+void launch_interp(int n, double box, const void* mesh, int mesh_fp32, int nc, const void* pos, int pos_fp32,
+                   long long np, double* out, hipStream_t s) {
+#define DGP_INTERP(NC)                                                                                        \
+  if (mesh_fp32) interp_m<float, NC>(n, box, static_cast<const float*>(mesh), pos, pos_fp32, np, out, s);     \
+  else interp_m<double, NC>(n, box, static_cast<const double*>(mesh), pos, pos_fp32, np, out, s);
+  switch (nc) {
+    case 1: DGP_INTERP(1) break;
+    case 2: DGP_INTERP(2) break;
+    default: DGP_INTERP(3) break;
+  }
+#undef DGP_INTERP
 }
-
-#ifndef DGP_GATHER_BINNED
-#define DGP_GATHER_BINNED 1
-#endif
 
 template <typename M>
 static void kick_m(int n, double box, const M* mesh3, void* pos, void* vel, int fp32, long long np, double kick,
                    double drift, hipStream_t s) {
   const double scale = double(n) / box;
-  if (DGP_GATHER_BINNED) {
-    const unsigned g = unsigned((np + kGatherChunk - 1) / kGatherChunk);
-    if (fp32)
-      hipLaunchKernelGGL((k_interp_kick_drift_bin<float, M>), dim3(g), dim3(256), 0, s, mesh3,
-                         static_cast<float*>(pos), static_cast<float*>(vel), np, n, scale, box, kick, drift);
-    else
-      hipLaunchKernelGGL((k_interp_kick_drift_bin<double, M>), dim3(g), dim3(256), 0, s, mesh3,
-                         static_cast<double*>(pos), static_cast<double*>(vel), np, n, scale, box, kick, drift);
-    return;
-  }
+  const unsigned g = unsigned((np + kGatherChunk - 1) / kGatherChunk);
   if (fp32)
-    hipLaunchKernelGGL((k_interp_kick_drift<float, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
-                       static_cast<float*>(pos), static_cast<float*>(vel), np, n, scale, box, kick, drift);
+    hipLaunchKernelGGL((k_interp_kick_drift_bin<float, M>), dim3(g), dim3(256), 0, s, mesh3, static_cast<float*>(pos),
+                       static_cast<float*>(vel), np, n, scale, box, kick, drift);
   else
-    hipLaunchKernelGGL((k_interp_kick_drift<double, M>), dim3(grid_for(np)), dim3(256), 0, s, mesh3,
+    hipLaunchKernelGGL((k_interp_kick_drift_bin<double, M>), dim3(g), dim3(256), 0, s, mesh3,
                        static_cast<double*>(pos), static_cast<double*>(vel), np, n, scale, box, kick, drift);
 }
 
@@ -546,6 +678,48 @@ void launch_deposit_backward(int n, double box, const void* pos, int pos_fp32, l
   else
     hipLaunchKernelGGL((k_deposit_backward<double>), dim3(grid_for(np)), dim3(256), 0, s,
                        static_cast<const double*>(pos), np, n, scale, grad_delta, mass, grad_pos);
+}
+
+void launch_zero_flag(int* bad, hipStream_t s) { hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, s, bad); }
+
+template <typename P, int NC>
+static void interp_bwd_t(int n, double box, const double* mesh, const P* pos, long long np, const double* g,
+                         double* grad_pos, double* grad_mesh, long long* grid, unsigned long long* st, int* bad,
+                         hipStream_t s) {
+  const double scale = double(n) / box;
+  const size_t n3 = (size_t)n * n * n;
+  if (grad_pos)
+    hipLaunchKernelGGL((k_interp_grad_pos<P, NC>), dim3(grid_for(np)), dim3(256), 0, s, mesh, pos, np, n, scale, g,
+                       grad_pos);
+  if (!grad_mesh) return;
+  auto* acc = reinterpret_cast<unsigned long long*>(grad_mesh);
+  launch_fill_zero(acc, NC * n3, s);
+  launch_fill_zero(grid, n3, s);
+  hipLaunchKernelGGL(k_zero_scale_state, dim3(1), dim3(64), 0, s, st, bad);
+  launch_deposit(n, box, pos, sizeof(P) == 4, np, grid, bad, s);
+  hipLaunchKernelGGL(k_max_abs_and_mass, dim3(grid_strided(n3)), dim3(256), 0, s, g, (size_t)NC * np, grid, n3, st,
+                     bad);
+  hipLaunchKernelGGL(k_interp_scale, dim3(1), dim3(64), 0, s, st);
+  const unsigned gch = unsigned((np + kDepChunk - 1) / kDepChunk);
+  hipLaunchKernelGGL((k_interp_grad_mesh_bin<P, NC>), dim3(gch), dim3(256), 0, s, pos, np, n, scale, g, st, acc);
+  hipLaunchKernelGGL(k_fixed_to_double, dim3(grid_strided(NC * n3)), dim3(256), 0, s, acc, NC * n3, st, bad);
+}
+
+void launch_interp_backward(int n, double box, const double* mesh, int nc, const void* pos, int pos_fp32, long long np,
+                            const double* g, double* grad_pos, double* grad_mesh, long long* grid,
+                            unsigned long long* st, int* bad, hipStream_t s) {
+#define DGP_IB(P, NC) \
+  interp_bwd_t<P, NC>(n, box, mesh, static_cast<const P*>(pos), np, g, grad_pos, grad_mesh, grid, st, bad, s)
+  if (pos_fp32) {
+    if (nc == 1) DGP_IB(float, 1);
+    else if (nc == 2) DGP_IB(float, 2);
+    else DGP_IB(float, 3);
+  } else {
+    if (nc == 1) DGP_IB(double, 1);
+    else if (nc == 2) DGP_IB(double, 2);
+    else DGP_IB(double, 3);
+  }
+#undef DGP_IB
 }
 
 template <typename T>

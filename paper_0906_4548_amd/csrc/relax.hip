@@ -38,26 +38,8 @@ const cx<T>* twiddles(int n);
 #ifndef DGP_RELAX_F32ACC
 #define DGP_RELAX_F32ACC 1
 #endif
-#ifndef DGP_RELAX_PREFETCH
-#define DGP_RELAX_PREFETCH 1
-#endif
-#ifndef DGP_RELAX_PRELOAD
-#define DGP_RELAX_PRELOAD 0
-#endif
-// float32: each thread loads the two spectral values of exactly the rows its transform
-// elements need (row e, or row N - e conjugated), skipping the LDS staging of the tile
-#ifndef DGP_RELAX_DIRECT
-#define DGP_RELAX_DIRECT 1
-#endif
-#ifndef DGP_RELAX_TWL
-#define DGP_RELAX_TWL 1
-#endif
-
 #ifndef DGP_RELAX_TP_F32
 #define DGP_RELAX_TP_F32 0
-#endif
-#ifndef DGP_RELAX_TP_F64
-#define DGP_RELAX_TP_F64 0
 #endif
 #ifndef DGP_RELAX_MINW_F32
 #define DGP_RELAX_MINW_F32 1
@@ -71,19 +53,21 @@ struct RelaxTile {
   static constexpr int kThreads = kTP * kT;
 };
 
+// geometry of the float32 relaxation kernel
 template <typename T, int N>
 struct RelaxGeo {
-  // at N >= 512 the spectral planes are 2 MB (float32) apart and a 128-byte row segment per
-  // plane streams poorly: float32 takes radix 8 and 16 column pairs (256-byte segments)
-  static constexpr bool kWide = sizeof(T) == 4 && N >= 512;
-  using P = typename PlanPick<N, (sizeof(T) == 4 ? (kWide ? 0 : DGP_PLAN_RELAX_F32) : DGP_PLAN_RELAX)>::type;
+  static_assert(sizeof(T) == 4, "the block-synchronous relaxation kernel is the float32 one");
+  // at N >= 512 the spectral planes are 2 MB apart and a 128-byte row segment per plane streams
+  // poorly: radix 8 and 16 column pairs (256-byte segments)
+  static constexpr bool kWide = N >= 512;
+  using P = typename PlanPick<N, (kWide ? 0 : DGP_PLAN_RELAX_F32)>::type;
   static constexpr int R = P::R;
-  using G = RelaxTile<T, N, R, (sizeof(T) == 4 ? (kWide ? 16 : DGP_RELAX_TP_F32) : DGP_RELAX_TP_F64)>;
+  using G = RelaxTile<T, N, R, (kWide ? 16 : DGP_RELAX_TP_F32)>;
   // minimum wavefronts per SIMD the register allocation plans for (second launch bound)
-  static constexpr int kMinWaves = sizeof(T) == 4 ? DGP_RELAX_MINW_F32 : 1;
-  // accumulators of the float32 form may be float32 (pointwise arithmetic in the
-  // precision of the fields); the residual, discriminant and root stay float64
-  using Acc = typename std::conditional<(sizeof(T) == 4 && DGP_RELAX_F32ACC), float, double>::type;
+  static constexpr int kMinWaves = DGP_RELAX_MINW_F32;
+  // accumulators of the float32 form (sum h^2 and -(h00 + h11)): float32 or float64; the
+  // residual, discriminant and root are float64 either way
+  using Acc = typename std::conditional<DGP_RELAX_F32ACC, float, double>::type;
 };
 
 // sum over the W lanes of a wavefront segment (butterfly order, deterministic)
@@ -163,6 +147,9 @@ __device__ __forceinline__ void relax_points(const PointCoef& k, const V (&up)[R
                              double(j ? nfv[q].y : nfv[q].x), double(s2[q][j]), double(h22[q][j]), abs_r, nbad);
 }
 
+// float32 kernel: block-synchronous transforms; each thread loads, one field ahead, exactly the
+// spectral rows its transform elements need (row e, or row N - e conjugated), so the tile is not
+// staged in LDS
 template <typename T, int N>
 __global__ void __launch_bounds__((RelaxGeo<T, N>::G::kThreads), (RelaxGeo<T, N>::kMinWaves))
 k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, const T* __restrict__ sfield,
@@ -174,13 +161,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   constexpr int R = P::R;
   using G = typename RG::G;
   constexpr int TP = G::kTP, TT = G::kT, H = N / 2 + 1;
-  constexpr int LSZ = (H * 2 * TP > N * TP) ? H * 2 * TP : N * TP;
-  constexpr int NPF = (H + TT - 1) / TT;   // tile rows loaded per thread
   constexpr size_t N3 = (size_t)N * N * N;
-  // the next field's tile is fetched into registers during the current transform
-  // (float only: for double the staging registers make the compiler spill)
-  constexpr bool kPrefetch = DGP_RELAX_PREFETCH && sizeof(T) == 4;
-  constexpr bool kDirect = DGP_RELAX_DIRECT && sizeof(T) == 4;
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
@@ -188,34 +169,19 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   xcd_tile(tile, i1);
   const int c = threadIdx.x % TP, t = threadIdx.x / TP;
   const int i2 = (tile * TP + c) * 2;
-  __shared__ cx<T> lds[LSZ];
+  __shared__ cx<T> lds[N * TP];
   __shared__ double red[(G::kThreads + 63) / 64];
   __shared__ int redi[(G::kThreads + 63) / 64];
   LdsCol<T, TP> L{lds, c};
   // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
-  // cached global loads at every stage (visible after the first barrier of the field loop)
-  __shared__ cx<T> twl[DGP_RELAX_TWL ? N : 1];
-  if constexpr (DGP_RELAX_TWL)
-    for (int i = threadIdx.x; i < N; i += G::kThreads) twl[i] = tw[i];
-  const cx<T>* twp = DGP_RELAX_TWL ? twl : tw;
+  // cached global loads at every stage
+  __shared__ cx<T> twl[N];
+  for (int i = threadIdx.x; i < N; i += G::kThreads) twl[i] = tw[i];
 
-  // software pipeline: the tile of field f+1 is fetched into registers while field f is transformed
   const size_t col = (size_t)b * H * N * N + (size_t)i1 * N + i2;
-  cx<T> pf[NPF][2];
-  auto fetch = [&](int f) {
-    const cx<T>* src = spec6 + f * fstride + col;
-#pragma unroll
-    for (int r = 0; r < NPF; ++r) {
-      const int k = t + r * TT;
-      if (k < H) {
-        pf[r][0] = src[(size_t)k * N * N];
-        pf[r][1] = src[(size_t)k * N * N + 1];
-      }
-    }
-  };
-  // direct loads: element q of thread t is row e = t + q TT of the Hermitian-extended column
-  // pair; rows e > N/2 come from row N - e (conjugated when used); streaming loads (the last
-  // use of these spectra in the pass)
+  // element q of thread t is row e = t + q TT of the Hermitian-extended column pair; rows e > N/2
+  // come from row N - e (conjugated when used); streaming loads (the last use of these spectra in
+  // the pass)
   cx<T> pd[R][2];
   auto fetch_direct = [&](int f) {
     const cx<T>* src = spec6 + f * fstride + col;
@@ -229,8 +195,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       pd[q][1] = mk(T(x.z), T(x.w));
     }
   };
-  if constexpr (kDirect) fetch_direct(0);
-  else if (kPrefetch) fetch(0);
+  fetch_direct(0);
 
   Acc s2[R][2], h22[R][2];
   cx<T> v[R];
@@ -239,72 +204,19 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   cx<T> up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    if constexpr (kDirect) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const int e = t + q * TT;
-        cx<T> xa = pd[q][0], xb = pd[q][1];
-        if (e > N / 2) {
-          xa = conjg(xa);
-          xb = conjg(xb);
-        }
-        if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
-        v[q] = mk(xa.x - xb.y, xa.y + xb.x);
-      }
-      if (f < 5) fetch_direct(f + 1);
-      else if (DGP_RELAX_PRELOAD) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const size_t off = (size_t)(t + q * TT) * N * N;
-          up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
-          spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
-        }
-      }
-    } else {
-    lds_barrier();
-    if constexpr (kPrefetch) {
-#pragma unroll
-      for (int r = 0; r < NPF; ++r) {
-        const int k = t + r * TT;
-        if (k < H) {
-          lds[k * 2 * TP + 2 * c] = pf[r][0];
-          lds[k * 2 * TP + 2 * c + 1] = pf[r][1];
-        }
-      }
-    } else {
-      const cx<T>* src = spec6 + f * fstride + col;
-      for (int k = t; k < H; k += TT) {
-        lds[k * 2 * TP + 2 * c] = src[(size_t)k * N * N];
-        lds[k * 2 * TP + 2 * c + 1] = src[(size_t)k * N * N + 1];
-      }
-    }
-    lds_barrier();
-    if (f < 5) {
-      if (kPrefetch) fetch(f + 1);
-    } else if (DGP_RELAX_PRELOAD) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const size_t off = (size_t)(t + q * TT) * N * N;
-        up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
-        spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
-      }
-    }
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int e = t + q * TT;
-      cx<T> xa, xb;
-      if (e <= N / 2) {
-        xa = lds[e * 2 * TP + 2 * c];
-        xb = lds[e * 2 * TP + 2 * c + 1];
-        if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
-      } else {
-        xa = conjg(lds[(N - e) * 2 * TP + 2 * c]);
-        xb = conjg(lds[(N - e) * 2 * TP + 2 * c + 1]);
+      cx<T> xa = pd[q][0], xb = pd[q][1];
+      if (e > N / 2) {
+        xa = conjg(xa);
+        xb = conjg(xb);
       }
-      v[q] = mk(xa.x - xb.y, xa.y + xb.x);
+      if (e == 0 || e == N / 2) { xa.y = T(0); xb.y = T(0); }
+      v[q] = mk(xa.x - xb.y, xa.y + xb.x);   // x_a + i x_b
     }
-    }
-    fft<T, N, P, +1>(v, twp, L, t);
+    if (f < 5) fetch_direct(f + 1);
+    fft<T, N, P, +1>(v, twl, L, t);
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -331,13 +243,11 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
   double abs_r = 0.0;
   int nbad = 0;
-  if (!DGP_RELAX_PRELOAD) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const size_t off = (size_t)(t + q * TT) * N * N;
-      up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
-      spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
-    }
+  for (int q = 0; q < R; ++q) {
+    const size_t off = (size_t)(t + q * TT) * N * N;
+    up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
+    spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
   }
   double un[R][2];
   relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
@@ -345,12 +255,11 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   for (int q = 0; q < R; ++q) {
     const size_t off = (size_t)(t + q * TT) * N * N;
     const cx<T> o = mk(T(un[q][0]), T(un[q][1]));
-    if constexpr (kDirect) store_stream(reinterpret_cast<cx<T>*>(uout + off), o);   // read again next pass only
-    else *reinterpret_cast<cx<T>*>(uout + off) = o;
+    store_stream(reinterpret_cast<cx<T>*>(uout + off), o);   // read again next pass only
     v[q] = o;
   }
   // forward axis-0 transform of u^(n+1)
-  fft<T, N, P, -1>(v, twp, L, t);
+  fft<T, N, P, -1>(v, twl, L, t);
   lds_barrier();
 #pragma unroll
   for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
@@ -386,69 +295,48 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 }
 
 
-// ------------------------------------------------------------------ wave-local variant
+// ------------------------------------------------------------------ float64 kernel (wave-local)
 // Same pass as k_relax, restructured so that each axis-0 transform is carried by the
 // lanes of one wavefront: its Stockham exchanges then need wavefront ordering only,
 // and the workgroup barriers drop from one pair per stage to one per field.  Global
 // traffic stays coalesced: spectral tiles are fetched row-wise into a double-buffered,
 // padded LDS tile; a transform reads its own two columns of the tile and reuses the
 // same slots (only its wavefront touches them) for the exchanges.
-#ifndef DGP_RELAXW_WAVE_F64
-#define DGP_RELAXW_WAVE_F64 1
-#endif
-#ifndef DGP_RELAXW_WAVE_F32
-#define DGP_RELAXW_WAVE_F32 0
-#endif
-
-#ifndef DGP_RELAXW_TP_F32
-#define DGP_RELAXW_TP_F32 0
-#endif
 #ifndef DGP_RELAXW_TP_F64
 #define DGP_RELAXW_TP_F64 0
-#endif
-#ifndef DGP_RELAXW_MINW_F32
-#define DGP_RELAXW_MINW_F32 1
 #endif
 #ifndef DGP_RELAXW_MINW_F64
 #define DGP_RELAXW_MINW_F64 3
 #endif
-#ifndef DGP_RELAXW_PRELOAD
-#define DGP_RELAXW_PRELOAD 1
-#endif
 
 template <typename T, int N>
 struct RelaxWGeo {
-  // float64 at N >= 512: radix 8 (one 512-point transform per wavefront) and 8 column pairs
-  static constexpr bool kWide = sizeof(T) == 8 && N >= 512;
+  static_assert(sizeof(T) == 8, "the wave-local relaxation kernel is the float64 one");
+  // at N >= 512: radix 8 (one 512-point transform per wavefront) and 8 column pairs
+  static constexpr bool kWide = N >= 512;
   using P = typename PlanPick<N, (kWide ? 0 : DGP_PLAN_RELAX)>::type;
   static constexpr int R = P::R;
   using G = AxisTile<T, N, R>;
-  static constexpr int kTPSet = sizeof(T) == 8 ? (kWide ? 8 : DGP_RELAXW_TP_F64) : DGP_RELAXW_TP_F32;
+  static constexpr int kTPSet = kWide ? 8 : DGP_RELAXW_TP_F64;
   static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
   static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
-  static constexpr int kMinWaves = sizeof(T) == 8 ? DGP_RELAXW_MINW_F64 : DGP_RELAXW_MINW_F32;
-  static constexpr bool kUse = (sizeof(T) == 8 ? DGP_RELAXW_WAVE_F64 : DGP_RELAXW_WAVE_F32) && (kT <= 64) &&
-                               (64 % kT == 0);
+  static constexpr int kMinWaves = DGP_RELAXW_MINW_F64;
+  static_assert(kT <= 64 && 64 % kT == 0, "a transform must stay inside one wavefront");
   static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
   static constexpr int kTile = H * kSP;
-  static constexpr bool kWave = (kT <= 64) && (64 % kT == 0);
   static constexpr int kNPF = (H * kTP + kThreads - 1) / kThreads;   // column pairs fetched per thread
   static constexpr int kWaves = (kThreads + 63) / 64;
   static constexpr int kWidth = kThreads < 64 ? kThreads : 64;       // lanes of a (possibly partial) wavefront
-  using Acc = typename RelaxGeo<T, N>::Acc;
 };
 
 // Exchange slots of transform c inside its own two tile columns (2c, 2c+1).
-template <typename T, int SP, bool WAVE>
+template <typename T, int SP>
 struct LdsPair {
   cx<T>* base;
   int c;
   __device__ __forceinline__ cx<T> load(int e) const { return base[(e >> 1) * SP + 2 * c + (e & 1)]; }
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[(e >> 1) * SP + 2 * c + (e & 1)] = v; }
-  __device__ __forceinline__ void sync() const {
-    if constexpr (WAVE) wave_sync();
-    else lds_barrier();
-  }
+  __device__ __forceinline__ void sync() const { wave_sync(); }
 };
 
 
@@ -460,11 +348,9 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
           const SolveCtl* __restrict__ ctl, const cx<T>* __restrict__ tw) {
   using W = RelaxWGeo<T, N>;
   using P = typename W::P;
-  using Acc = typename W::Acc;
   constexpr int R = W::R, TP = W::kTP, TT = W::kT, NT = W::kThreads, H = N / 2 + 1, SP = W::kSP;
   constexpr int NPF = W::kNPF;
   constexpr size_t N3 = (size_t)N * N * N, NN = (size_t)N * N;
-  constexpr bool kPreload = DGP_RELAXW_PRELOAD && sizeof(T) == 4;   // u and S fetched during the last transform
   const int b = blockIdx.z;
   if (ctl[b].done) return;
   const int cur = ctl[b].cur, nxt = ctl[b].out;
@@ -507,7 +393,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
 
   const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
   const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
-  Acc s2[R][2], h22[R][2];
+  double s2[R][2], h22[R][2];
   cx<T> v[R], up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
@@ -528,22 +414,13 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
       }
       v[q] = mk(xa.x - xb.y, xa.y + xb.x);
     }
-    if (f < 5) {
-      fetch(f + 1);
-    } else if (kPreload) {
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const size_t off = (size_t)(t + q * TT) * NN;
-        up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
-        spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
-      }
-    }
-    LdsPair<T, SP, W::kWave> X{buf, c};
+    if (f < 5) fetch(f + 1);
+    LdsPair<T, SP> X{buf, c};
     fft<T, N, P, +1>(v, tw, X, t);
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const Acc hx = Acc(v[q].x), hy = Acc(v[q].y);
+        const double hx = v[q].x, hy = v[q].y;
         if (f == 0) {
           s2[q][0] = hx * hx;
           s2[q][1] = hy * hy;
@@ -555,8 +432,8 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
           h22[q][0] -= hx;
           h22[q][1] -= hy;
         } else {
-          s2[q][0] += Acc(2) * hx * hx;
-          s2[q][1] += Acc(2) * hy * hy;
+          s2[q][0] += 2.0 * hx * hx;
+          s2[q][1] += 2.0 * hy * hy;
         }
       }
     }
@@ -566,13 +443,11 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   T* ust = reinterpret_cast<T*>(lds);
   double abs_r = 0.0;
   int nbad = 0;
-  if (!kPreload) {
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int e = t + q * TT;
-      up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
-      spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
-    }
+  for (int q = 0; q < R; ++q) {
+    const int e = t + q * TT;
+    up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
+    spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
   }
   double un[R][2];
   relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
@@ -586,7 +461,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   }
   // forward axis-0 transform of u^(n+1), exchanges in the transform's own columns of tile 1
   {
-    LdsPair<T, SP, W::kWave> X{lds + W::kTile, c};
+    LdsPair<T, SP> X{lds + W::kTile, c};
     fft<T, N, P, -1>(v, tw, X, t);
   }
   abs_r = wave_sum<W::kWidth>(abs_r);
@@ -661,7 +536,8 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
         sb[0] += sb[i];
       }
       SolveCtl& C = ctl[b];
-      const double r = sr[0] / (n3 * C.eps);
+      // eps = 0 only for a uniform delta (S = 0), whose exact solution u = 0 has R = 0
+      const double r = C.eps > 0.0 ? sr[0] / (n3 * C.eps) : (sr[0] == 0.0 ? 0.0 : __builtin_huge_val());
       const int nbad = int(sb[0]);
       const int n = C.iters;
       if (n < kMaxHist) {
@@ -670,7 +546,12 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
       }
       C.passes += 1;
       bool done = false;
-      if (r <= cfg.tol) {
+      if (r != r) {   // a non-finite iterate (non-finite warm start, or divergence): nothing to return
+        C.status = kStatusInvalid;
+        C.result = C.cur;
+        C.resid = r;
+        done = true;
+      } else if (r <= cfg.tol) {
         C.status = 0;
         C.result = C.cur;
         C.resid = r;
@@ -768,14 +649,14 @@ k_absmean_final(const double* __restrict__ part, int groups, size_t n3, double* 
 template <typename T, int N>
 static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
                     const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
-  using G = typename RelaxGeo<T, N>::G;
-  using W = RelaxWGeo<T, N>;
   constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
-  if constexpr (W::kUse) {
+  if constexpr (sizeof(T) == 8) {
+    using W = RelaxWGeo<T, N>;
     dim3 grid(N / (2 * W::kTP), N, batch);
     hipLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(W::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield,
                        spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
   } else {
+    using G = typename RelaxGeo<T, N>::G;
     dim3 grid(N / (2 * G::kTP), N, batch);
     hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
                        partial, mean_u, cfg, ctl, twiddles<T>(N));
@@ -800,7 +681,8 @@ void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* sp
 // column pairs per workgroup of the relaxation kernel that launches for (T, N)
 template <typename T, int N>
 static constexpr int relax_tp() {
-  return RelaxWGeo<T, N>::kUse ? RelaxWGeo<T, N>::kTP : RelaxGeo<T, N>::G::kTP;
+  if constexpr (sizeof(T) == 8) return RelaxWGeo<T, N>::kTP;
+  else return RelaxGeo<T, N>::G::kTP;
 }
 
 int relax_groups(int n, int elem_bytes) {
@@ -841,6 +723,14 @@ __device__ void ctl_reset(SolveCtl& C) {
   }
 }
 
+// a non-finite eps means a non-finite delta (or position): the element is decided at once as invalid
+__device__ __forceinline__ void mark_invalid_input(SolveCtl& C) {
+  if (!isfinite(C.eps)) {
+    C.done = 1;
+    C.status = kStatusInvalid;
+  }
+}
+
 __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, int batch) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
@@ -850,6 +740,7 @@ __global__ void k_ctl_init(SolveCtl* __restrict__ ctl, const double* __restrict_
   C.iters1 = 0;
   C.passes1 = 0;
   C.phase1_done = 1;
+  mark_invalid_input(C);
 }
 
 // -1: the float32 phase met its tolerance on the initial guess itself, whose float64 form
@@ -899,10 +790,15 @@ __global__ void k_ctl_phase2(SolveCtl* __restrict__ ctl, int batch) {
   if (b >= batch) return;
   SolveCtl& C = ctl[b];
   const int src = handoff_buffer(C);
+  const bool invalid = C.status == kStatusInvalid;
   C.iters1 = C.iters + ((C.done && src == C.out) ? 1 : 0);
   C.passes1 = C.passes;
   C.phase1_done = C.done;
   ctl_reset(C);
+  if (invalid) {
+    C.done = 1;
+    C.status = kStatusInvalid;
+  }
 }
 
 static int absmean_groups(size_t n3) {
@@ -974,6 +870,7 @@ k_ctl_spherical(SolveCtl* __restrict__ ctl, const double* __restrict__ eps, cons
   C.resid_min = -1.0;
   C.bad_frac = (((rb[0] + rb[1]) + rb[2]) + rb[3]) / double(n3);
   C.hist_bad[0] = C.bad_frac;
+  mark_invalid_input(C);
 }
 
 void launch_spherical(size_t n3, int batch, const double* S, double* u, double alpha, double lam, double* partial,

@@ -162,6 +162,27 @@ class Plan:
             _ptr(grad_delta, torch.float64, self.n3, "grad_delta"),
             _ptr(grad_pos, torch.float64, 3 * npart, "grad_pos"), _stream()))
 
+    def interp(self, mesh, pos, out):
+        """CIC interpolation out [ncomp, np] of mesh [ncomp, N^3] (float64) at pos [3, np]."""
+        npart = pos.shape[-1]
+        nc = mesh.numel() // self.n3
+        fp32 = 1 if pos.dtype == torch.float32 else 0
+        return check(_lib.load().dgp_interp(
+            self.handle, _ptr(mesh, torch.float64, nc * self.n3, "mesh"), nc, _ptr(pos, None, 3 * npart, "pos"), fp32,
+            npart, _ptr(out, torch.float64, nc * npart, "out"), _stream()))
+
+    def interp_backward(self, mesh, pos, grad_out, grad_pos=None, grad_mesh=None):
+        """Adjoint of interp: grad_pos [3, np] and/or grad_mesh [ncomp, N^3] (float64) from
+        grad_out [ncomp, np]; mesh is needed only for grad_pos."""
+        npart = pos.shape[-1]
+        nc = grad_out.numel() // npart
+        fp32 = 1 if pos.dtype == torch.float32 else 0
+        return check(_lib.load().dgp_interp_backward(
+            self.handle, _ptr(mesh, torch.float64, nc * self.n3, "mesh"), nc, _ptr(pos, None, 3 * npart, "pos"), fp32,
+            npart, _ptr(grad_out, torch.float64, nc * npart, "grad_out"),
+            _ptr(grad_pos, torch.float64, 3 * npart, "grad_pos"),
+            _ptr(grad_mesh, torch.float64, nc * self.n3, "grad_mesh"), _stream()))
+
     def power_spectrum(self, prm, field, of_c=False, nbins=64):
         """Returns (pk [batch, nbins] numpy, counts [nbins] numpy)."""
         pk = np.zeros((self.batch, nbins))
