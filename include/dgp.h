@@ -77,7 +77,10 @@ typedef struct {
   double lambda;       /* coefficient of the two quadratic terms of Eq. FullDGP2 (1 = paper); > 0 */
   double w;            /* split of Eq. FullDGP2wpara, in [0, 1); paper: 1/3 */
   double omega_relax;  /* damping u <- (1-omega) u + omega u_new, in (0, 1]; paper: 1 */
-  double tol;          /* stop when <|R|>/eps <= tol (Eq. normres); paper: 0.01 */
+  double tol;          /* stop when <|R|>/eps <= tol (Eq. normres); paper: 0.01.  tol < 0: no stopping
+                          test, exactly max_iter updates and the last iterate returned with DGP_OK
+                          (reproducible update counts, e.g. for finite differences); the adjoint
+                          takes tol < 0 as "run max_iter iterations" (DGP_NOT_CONVERGED) */
   int max_iter;        /* maximum number of relaxation updates (>= 0) */
   int init;            /* dgp_init: starting iterate */
   int nonlocal;        /* 1 keeps the sqrt(-lap) and lap^{-1/2} terms (paper), 0 drops them */
@@ -167,8 +170,9 @@ int dgp_step(dgp_plan* plan, const dgp_params* p, void* pos, void* vel, int is_f
  * delta, u_star, grad_u, grad_delta: [batch][N^3] float64.  Uses p->tol as the relative
  * tolerance on <|J^T mu - g|>/<|g|> and p->max_iter; at max_iter the minimum-residual mu is
  * used and DGP_NOT_CONVERGED returned.  DGP_E_INVALID when u_star has points with
- * D = 2 (1-w) lam u + alpha <= 0 (the vertex value of a bad point: the solve did not converge
- * there and the transposed relaxation would divide by zero) or non-finite values, or when
+ * D = 2 (1-w) lam u + alpha <= 1e-12 alpha (the vertex value of a bad point, up to rounding: the
+ * solve did not converge there and the transposed relaxation would divide by about zero) or
+ * non-finite values, or when
  * grad_u is not finite.  Synchronises once per transposed-relaxation iteration. */
 int dgp_solve_field_backward(dgp_plan* plan, const dgp_params* p, const double* delta, const double* u_star,
                              const double* grad_u, double* grad_delta, dgp_info* info, void* stream);

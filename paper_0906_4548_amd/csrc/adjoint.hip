@@ -19,9 +19,10 @@
 
 namespace dgp {
 
-// mu = g / D; per workgroup, the number of points where D = 2 (1-w) lam u + alpha is not positive
-// (the vertex value of a bad point gives D = 0: there the implicit adjoint does not exist) or not
-// finite, and the number of non-finite g (part[b][group][0..1])
+// mu = g / D; per workgroup, the number of points where D = 2 (1-w) lam u + alpha is at most
+// dmin = 1e-12 alpha (the vertex value of a bad point gives D = 0 up to rounding: there the
+// implicit adjoint does not exist) or not finite, and the number of non-finite g
+// (part[b][group][0..1])
 __global__ void __launch_bounds__(256)
 k_adj_init(size_t n3, const double* __restrict__ g, const double* __restrict__ u, double* __restrict__ mu,
            double dscale, double alpha, double* __restrict__ part) {
@@ -31,7 +32,7 @@ k_adj_init(size_t n3, const double* __restrict__ g, const double* __restrict__ u
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
     const double d = dscale * u[off + i] + alpha;
     const double gg = g[off + i];
-    nd += (d > 0.0 && isfinite(d)) ? 0.0 : 1.0;
+    nd += (d > 1e-12 * alpha && isfinite(d)) ? 0.0 : 1.0;
     ng += isfinite(gg) ? 0.0 : 1.0;
     mu[off + i] = gg / d;
   }

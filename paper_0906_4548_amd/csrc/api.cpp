@@ -165,7 +165,6 @@ static int check_params(const dgp_params* p) {
   if (!(p->lambda > 0.0)) return fail(DGP_E_INVALID, "lambda must be > 0");
   if (!(p->w >= 0.0 && p->w < 1.0)) return fail(DGP_E_INVALID, "w must be in [0, 1)");
   if (!(p->omega_relax > 0.0 && p->omega_relax <= 1.0)) return fail(DGP_E_INVALID, "omega_relax must be in (0, 1]");
-  if (!(p->tol >= 0.0)) return fail(DGP_E_INVALID, "tol must be >= 0");
   if (p->max_iter < 0 || p->max_iter >= kMaxHist - 1) return fail(DGP_E_INVALID, "max_iter must be in [0, %d)", kMaxHist - 1);
   if (p->init < 0 || p->init > 2) return fail(DGP_E_INVALID, "bad init");
   if (p->force_mode < 0 || p->force_mode > 2) return fail(DGP_E_INVALID, "bad force_mode");
@@ -438,6 +437,7 @@ static SolveCfg solve_cfg(const dgp_plan* pl, const dgp_params* p, double tol, i
   c.omega = p->omega_relax;
   c.tol = tol;
   c.max_iter = max_iter;
+  c.fixed = p->tol < 0.0 ? 1 : 0;
   c.n = pl->n;
   c.batch = pl->batch;
   return c;
@@ -528,6 +528,7 @@ static int run_loop(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const SolveCfg&
   const int cap = p->check_every > 0 ? p->check_every : 4;
   int k = 0;
   int chunk = std::min(first > 0 ? first : 2, cfg.max_iter + 1);
+  if (cfg.fixed && cfg.tol < 0.0) chunk = cfg.max_iter + 1;   // every pass is known in advance
   for (;;) {
     for (int i = 0; i < chunk && k <= cfg.max_iter; ++i, ++k) TRY(enqueue_pass<T>(pl, p, w, cfg, s));
     if (!check) return DGP_OK;
@@ -1118,8 +1119,9 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   HIPCHK(hipStreamSynchronize(s));
   for (int b = 0; b < B; ++b) {
     if (host[b] > 0.0)
-      return fail(DGP_E_INVALID, "batch element %d: u* has points where 2 (1-w) lam u + alpha <= 0 (bad-point "
-                  "vertices of an unconverged solve) or non-finite values; the implicit adjoint does not exist there", b);
+      return fail(DGP_E_INVALID, "batch element %d: u* has points where 2 (1-w) lam u + alpha <= 1e-12 alpha "
+                  "(bad-point vertices of an unconverged solve) or non-finite values; the implicit adjoint does not "
+                  "exist there", b);
     if (host[B + b] > 0.0) return fail(DGP_E_INVALID, "batch element %d: grad_u is not finite", b);
   }
   std::vector<int> done(B, 0), iters(B, 0);

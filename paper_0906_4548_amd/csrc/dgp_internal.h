@@ -74,6 +74,7 @@ struct SolveCtl {
 struct SolveCfg {
   double lam, w, alpha, gamma, omega, tol;
   int max_iter;
+  int fixed;        // 1: exactly max_iter updates, the last iterate returned (no minimum-residual stop)
   int n;            // mesh size
   int batch;
 };

@@ -560,7 +560,7 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
       } else if (r < C.resid_min) {
         C.resid_min = r;
         C.best = C.cur;
-      } else if (C.bad_seen) {
+      } else if (C.bad_seen && !cfg.fixed) {
         C.status = 2;
         C.result = C.best;
         C.resid = C.resid_min;
@@ -568,9 +568,15 @@ k_finalize(const double* __restrict__ partial, int groups, SolveCtl* __restrict_
       }
       if (r < C.resid_min) C.resid_min = r;
       if (!done && n + C.iters1 >= cfg.max_iter) {
-        C.status = 1;
-        C.result = C.best;
-        C.resid = C.resid_min;
+        if (cfg.fixed) {   // the requested number of updates: the last iterate
+          C.status = 0;
+          C.result = C.cur;
+          C.resid = r;
+        } else {
+          C.status = 1;
+          C.result = C.best;
+          C.resid = C.resid_min;
+        }
         done = true;
       }
       if (!done) {

@@ -161,6 +161,31 @@ def test_solve_bad_points_same_sequence(dgp):
         assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-9
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fixed_update_mode(dgp, prec):
+    """tol < 0: exactly max_iter updates and the last iterate, the oracle's fixed_iters, also
+    through the bad-point regime where the stopping rule would end the solve (w = 0, z = 4)."""
+    say("fixed updates", prec)
+    n, box = 16, 32.0
+    delta = inputs.lognormal_delta(n, box, 1.5, 21)
+    k = 9
+    op = fld.SolveParams.from_cosmology(OM0, 0.2, lam=1.0, w=0.0, init=fld.INIT_ZERO)
+    u_ref, iref = fld.solve(delta, box, op, fixed_iters=k)
+    assert max(iref.bad_history) > 0
+    with dgp.Plan(n, box, precision=prec) as plan:
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        p = dgp.params(OM0, 0.2, lam=1.0, w=0.0, tol=-1.0, max_iter=k, init=dgp.INIT_ZERO)
+        st, info = plan.solve_field(p, to_dev(delta), u)
+        assert st == 0 and info[0]["iters"] == k
+        if prec == 0:
+            hist, bad = plan.history()
+            assert np.max(np.abs(hist - np.asarray(iref.history)) / np.asarray(iref.history)) <= 1e-9
+            assert np.array_equal(bad[:k], np.asarray(iref.bad_history))
+            assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-9
+        else:
+            assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-4
+
+
 def test_solve_batched_fp64(dgp):
     """Independent fields in one batched launch; each stops on its own (config C5 shape, smaller mesh)."""
     say("solve batched")
