@@ -132,6 +132,17 @@ size_t dgp_plan_device_bytes(const dgp_plan* plan);
 int dgp_deposit(dgp_plan* plan, const void* pos, int pos_is_fp32, long long np, long long* grid_fixed,
                 double* delta, void* stream);
 
+/* dgp_deposit without a plan and without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arithmetic and outputs (the same bits) as dgp_deposit on an N^3 mesh of side `box`;
+ * grid_fixed [N^3] int64 and delta [N^3] float64 are both required, N a power of two in [8, 512].
+ * The mean removal's partial sums, the mean and the non-finite flag live in a 32 KiB static
+ * device array that each GPU holds until the process ends; all calls on one device share it, so
+ * calls that overlap on one device race.  Enqueues fill kernels (no memset nodes) and allocates
+ * nothing.  Asynchronous; a non-finite position makes delta NaN, as for dgp_deposit. */
+int dgp_deposit_noalloc(int n, double box, const void* pos, int pos_is_fp32, long long np, long long* grid_fixed,
+                        double* delta, void* stream);
+
 /* Field solve of Eq. FullDGP2 by FFT-relaxation (Sec. III B, Eq. FFTrelax; w-split of
  * Sec. III C, Eqs. nabla^2Cwpara and Bwpara).
  * delta   [batch][N^3] float64 density contrast (its mean is ignored: k = 0 multipliers are 0).

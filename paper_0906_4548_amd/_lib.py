@@ -14,7 +14,7 @@ DGP_FORCE_NLDGP, DGP_FORCE_LDGP, DGP_FORCE_GRH = 0, 1, 2
 EXPORTS = (
     "dgp_params_init", "dgp_plan_create", "dgp_plan_destroy", "dgp_plan_device_bytes",
     "dgp_deposit", "dgp_solve_field", "dgp_pm_forces", "dgp_step", "dgp_solve_field_backward",
-    "dgp_deposit_backward", "dgp_interp", "dgp_interp_backward", "dgp_power_spectrum", "dgp_power_spectrum_backward",
+    "dgp_deposit_backward", "dgp_deposit_noalloc", "dgp_interp", "dgp_interp_backward", "dgp_power_spectrum", "dgp_power_spectrum_backward",
     "dgp_fft_forward", "dgp_fft_inverse", "dgp_timing_enable", "dgp_timing_classes", "dgp_timing_read",
     "dgp_run", "dgp_solve_history", "dgp_diagnostics", "dgp_last_error",
 )
@@ -64,6 +64,8 @@ def load():
                                     P(Info), vp]),
         "dgp_solve_field_backward": (ctypes.c_int, [vp, P(Params), vp, vp, vp, vp, P(Info), vp]),
         "dgp_deposit_backward": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_longlong, vp, vp, vp]),
+        "dgp_deposit_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, vp, ctypes.c_int, ctypes.c_longlong, vp,
+                                               vp, vp]),
         "dgp_interp": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_longlong, vp, vp]),
         "dgp_interp_backward": (ctypes.c_int, [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_longlong, vp, vp, vp,
                                                vp]),

@@ -887,6 +887,32 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
   return collect_finish(pl, info, ms);
 }
 
+extern "C" int dgp_deposit_noalloc(int n, double box, const void* pos, int pos_is_fp32, long long np,
+                                   long long* grid_fixed, double* delta, void* stream) {
+  if (!pos || !grid_fixed || !delta || np < 1) return fail(DGP_E_INVALID, "pos, grid_fixed, delta and np >= 1 are required");
+  if (n < 8 || n > 512 || (n & (n - 1)) != 0) return fail(DGP_E_INVALID, "N must be a power of two in [8, 512], got %d", n);
+  if (!(box > 0.0) || !std::isfinite(box)) return fail(DGP_E_INVALID, "box must be > 0");
+  double* sc = nullptr;
+  size_t cap = 0;
+  const int r = noalloc_scratch(&sc, &cap);
+  if (r != 0) return fail(r == -2 ? DGP_E_UNSUPPORTED : DGP_E_HIP, "device scratch of the allocation-free deposit unavailable");
+  const size_t n3 = (size_t)n * n * n;
+  const size_t parts = absmean_scratch_doubles(n3, 1);
+  if (parts + 4 > cap)
+    return fail(DGP_E_INVALID, "N = %d needs %zu scratch doubles, the allocation-free deposit has %zu", n, parts + 4, cap);
+  double* mean = sc + parts;
+  int* flag = reinterpret_cast<int*>(sc + parts + 2);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  launch_fill_zero(grid_fixed, n3, s);
+  launch_zero_flag(flag, s);
+  launch_deposit(n, box, pos, pos_is_fp32, np, grid_fixed, flag, s);
+  launch_counts_to_delta(n, grid_fixed, np, delta, flag, s);
+  launch_absmean<double>(n3, delta, 1, sc, nullptr, mean, s);
+  launch_sub_mean(n3, delta, 1, mean, s);
+  LAUNCHCHK();
+  return DGP_OK;
+}
+
 extern "C" int dgp_interp(dgp_plan* pl, const double* mesh, int ncomp, const void* pos, int pos_is_fp32, long long np,
                           double* out, void* stream) {
   if (!pl || !mesh || !pos || !out || np < 1) return fail(DGP_E_INVALID, "plan, mesh, pos, out and np >= 1 are required");

@@ -232,4 +232,8 @@ void launch_interp_backward(int n, double box, const double* mesh, int nc, const
 template <typename T>
 void launch_convert(size_t count, const void* in, int in_fp32, T* out, hipStream_t s);
 
+// per-device address and size (doubles) of the allocation-free deposit's static scratch;
+// 0 on success, -1 when the HIP runtime fails, -2 for a device index beyond the table
+int noalloc_scratch(double** ptr, size_t* capacity);
+
 }  // namespace dgp

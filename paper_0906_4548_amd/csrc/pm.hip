@@ -7,6 +7,8 @@
 // order independent: per-axis weights (1 - f, f) in FP64 with no fused
 // multiply-add, the 3D weight as (w_x w_y) w_z, quantised to Q = rint(W 2^40)
 // and summed with 64-bit integer atomics.
+#include <mutex>
+
 #include "dgp_internal.h"
 
 namespace dgp {
@@ -720,6 +722,32 @@ void launch_interp_backward(int n, double box, const double* mesh, int nc, const
     else DGP_IB(double, 3);
   }
 #undef DGP_IB
+}
+
+// ------------------------------------------------------------------ allocation-free deposit scratch
+// Device scratch of the allocation-free deposit entry point: the per-workgroup partial sums of the
+// mean removal, the mean and the non-finite flag.  One copy per device, held until the process
+// ends; every call on a device shares it, so calls that overlap on one device race.  Host code
+// uses the per-device address from hipGetSymbolAddress, never the array's name.
+constexpr size_t kNoallocScratchDoubles = 4096;   // 32 KiB
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+static void* g_noalloc_ptr[64];
+static std::mutex g_noalloc_mu;
+
+int noalloc_scratch(double** ptr, size_t* capacity) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  if (dev < 0 || dev >= 64) return -2;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {   // once per device, with that device current
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return -1;
+    g_noalloc_ptr[dev] = p;
+  }
+  *ptr = static_cast<double*>(g_noalloc_ptr[dev]);
+  *capacity = kNoallocScratchDoubles;
+  return 0;
 }
 
 template <typename T>
