@@ -17,6 +17,8 @@ Other modes:
   --trace-summary T       per-kernel duration table of a rocprofv3 kernel trace
   --stages                per-stage times of a PM step on a 512^3 mesh with 512^3 float32
                           particles (box 1024 Mpc/h), precision form and plain float64 form
+  --wscan                 the w-scan of Fig. 3 at the paper's size (z = 24, box 64 Mpc/h,
+                          256^3 mesh, 128^3 particles): residual and bad fraction per pass
 
 The solve runs in the precision form (float32 FFTs and pointwise storage,
 float64 residual / discriminant / root / reductions, float64 polish); the plain
@@ -261,6 +263,72 @@ def stages_512(args, torch, dgp, inputs, dev):
     print(json.dumps(out))
 
 
+def wscan(args, torch, dgp, inputs, dev):
+    """One JSON line: the convergence histories of Fig. 3 (Sec. III C) at the paper's size.  A seeded
+    Zel'dovich load of 128^3 particles (P ~ k^-1.5 exp(-k^2/k_c^2), k_c = 4 h/Mpc, rms displacement
+    0.15 Mpc/h) deposited on a 256^3 mesh of a 64 Mpc/h box, z = 24, lam = 1 (the paper's
+    equation); for each w the solve starts from the same linear solution and runs 40 updates
+    (float64), recording the normalised residual of every evaluated iterate and the bad fraction
+    of every update."""
+    n, box, nside, k = 256, 64.0, 128, 40
+    print("bench: building the z = 24 load", file=sys.stderr, flush=True)
+    pos, _ = inputs.zeldovich_load(nside, box, 24, slope=-1.5, kc=4.0, rms_disp=0.15)
+    out = {"mode": "wscan", "config": {"workload": "Fig. 3 w-scan: Zel'dovich load 128^3 particles on a 256^3 mesh, "
+                                                   "box 64 Mpc/h, z=24, lam=1, 40 updates from the linear solution",
+                                       "mesh": n, "particles": nside ** 3, "updates": k}, "runs": {}}
+    with dgp.Plan(n, box) as plan:
+        delta = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
+        plan.deposit(torch.from_numpy(pos).to(dev), None, delta)
+        out["config"]["delta_min"] = float(delta.min())
+        out["config"]["delta_rms"] = float(delta.std())
+        for w in (0.0, 0.25, 1.0 / 3.0, 0.5, 0.8):
+            u = torch.zeros_like(delta)
+            st, info = plan.solve_field(dgp.params(OM0, 1.0 / 25.0, lam=1.0, w=w, tol=-1.0, max_iter=k), delta, u)
+            hist, bad = plan.history(cap=k + 1)
+            out["runs"]["%.4f" % w] = {"status": st, "resid": hist.tolist(), "bad_fraction": bad[:k].tolist(),
+                                       "ms": info[0]["ms_total"]}
+    print(json.dumps(out))
+
+
+def fft_comparison(torch, dgp, dev, n=N, reps=10):
+    """The library's 3D real transform (three axis passes, float64) against torch.fft (rocFFT) on
+    the same 256^3 field: milliseconds per forward (R2C) and inverse (C2R) transform, HIP events
+    on the current stream, after a warm-up call of each."""
+    x = torch.randn(n, n, n, dtype=torch.float64, device=dev)
+    spec = torch.zeros((n // 2 + 1, n, n), dtype=torch.complex128, device=dev)
+    back = torch.zeros_like(x)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    with dgp.Plan(n, BOX) as plan:
+        ours_f = timed(lambda: plan.fft_forward(x, spec))
+        ours_i = timed(lambda: plan.fft_inverse(spec, back))
+    tk = {}
+    tk["r2c"] = timed(lambda: torch.fft.rfftn(x))
+    xk = torch.fft.rfftn(x)
+    tk["c2r"] = timed(lambda: torch.fft.irfftn(xk, s=(n, n, n)))
+    x32 = x.float()
+    tk["r2c_fp32"] = timed(lambda: torch.fft.rfftn(x32))
+    xk32 = torch.fft.rfftn(x32)
+    tk["c2r_fp32"] = timed(lambda: torch.fft.irfftn(xk32, s=(n, n, n)))
+    del x, spec, back, xk, x32, xk32
+    torch.cuda.empty_cache()
+    return {"mesh": n, "dgp_fp64_forward_ms": ours_f, "dgp_fp64_inverse_ms": ours_i,
+            "torch_fft_fp64_r2c_ms": tk["r2c"], "torch_fft_fp64_c2r_ms": tk["c2r"],
+            "torch_fft_fp32_r2c_ms": tk["r2c_fp32"], "torch_fft_fp32_c2r_ms": tk["c2r_fp32"],
+            "note": "dgp forward includes writing the spectrum in the plan's layout (half axis first); "
+                    "torch.fft dispatches to rocFFT"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +341,7 @@ def main():
                     help="write the calibrated traffic summary from two counter passes to stdout")
     ap.add_argument("--stages", action="store_true",
                     help="per-stage times of a 512^3 PM step with 512^3 float32 particles, both forms")
+    ap.add_argument("--wscan", action="store_true", help="the w-scan of Fig. 3 at the paper's size")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="write a per-kernel duration table from a rocprofv3 kernel trace to stdout")
     args = ap.parse_args()
@@ -294,6 +363,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.stages:
         stages_512(args, torch, dgp, inputs, dev)
+        return
+    if args.wscan:
+        wscan(args, torch, dgp, inputs, dev)
         return
     print("bench: building inputs", file=sys.stderr, flush=True)
     pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED, block=BLOCK)
@@ -354,7 +426,7 @@ def main():
     # Per-class breakdown on a short run with every class timed (two event records per launch).
     # The timed run that gives `value` then carries events on the dominant class only.
     print("bench: kernel breakdown", file=sys.stderr, flush=True)
-    _, _, tim_all = run_form(dgp.FP32, BREAKDOWN_STEPS, 1)
+    _, infos_all, tim_all = run_form(dgp.FP32, BREAKDOWN_STEPS, 1)
     dom = max((k for k in tim_all if (k[:-5] if k.endswith("_fp32") else k) in
                ("axis1_fwd", "fanout", "axis1_inv", "relax")), key=lambda k: tim_all[k][0])
     print("bench: timing precision form", file=sys.stderr, flush=True)
@@ -400,14 +472,20 @@ def main():
                        "unit": "GB/s", "frac": bpl / avg_s / PEAK_HBM, "traffic": stored_traffic(dom),
                        "bytes_per_launch": bpl, "avg_us": avg_s * 1e6, "launches": tim32[dom][1],
                        "working_launches": working}
+    # per-class rates over the launches that did a pass (launches after convergence exit at once)
+    pa = sum(i["passes"] for _, i in infos_all)
+    pa64 = sum(i["passes_fp64"] for _, i in infos_all)
     gbs = {}
     for k, (ms, cnt) in tim_all.items():
         b = k[:-5] if k.endswith("_fp32") else k
         e = 4 if k.endswith("_fp32") else 8
         bb = algorithmic_bytes(b, N, e)
         if bb:
-            gbs[k] = bb * cnt / (ms * 1e-3) / 1e9
+            gbs[k] = bb * ((pa - pa64) if k.endswith("_fp32") else pa64) / (ms * 1e-3) / 1e9
     res["kernel_GBps"] = gbs
+    res["kernel_GBps_note"] = "algorithmic bytes x working launches / class time (breakdown run)"
+    print("bench: FFT comparison", file=sys.stderr, flush=True)
+    res["fft_comparison"] = fft_comparison(torch, dgp, dev)
 
     if not args.no_fp64:
         print("bench: timing float64 form", file=sys.stderr, flush=True)
@@ -426,30 +504,71 @@ def main():
 
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(pos_h, lam)
+        res["cpu_baseline"] = cpu_baseline(pos_h, growth * psi_h, lam)
     print(json.dumps(res))
 
 
-def cpu_baseline(pos_h, lam):
-    """The CPU oracle (NumPy float64, pocketfft, one thread) on a bounded sample:
-    two relaxation passes of the same 256^3 solve, scaled to cells*iter/s."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_step(pos_h, vel_h, lam, tols):
+    """One PM step of the CPU oracle on the benchmark's load: deposit, the field solve from the
+    linear guess to each tolerance in `tols` (the step uses the first), forces, kick-drift.
+    Returns per-stage seconds and the passes of each solve."""
     from oracle import field as fld, pm
+    t = {}
     t0 = time.perf_counter()
     _, delta = pm.deposit(pos_h, N, BOX)
-    t_dep = time.perf_counter() - t0
-    prm = fld.SolveParams.from_cosmology(OM0, A, lam=lam, tol=TOL)
+    t["deposit"] = time.perf_counter() - t0
+    solves = {}
+    u = None
+    for tol in tols:
+        prm = fld.SolveParams.from_cosmology(OM0, A, lam=lam, tol=tol, max_iter=200)
+        t0 = time.perf_counter()
+        uu, info = fld.solve(delta, BOX, prm)
+        solves["%g" % tol] = {"seconds": time.perf_counter() - t0, "passes": info.iters + 1, "resid": info.resid}
+        u = uu if u is None else u
+    prm = fld.SolveParams.from_cosmology(OM0, A, lam=lam, tol=tols[0], max_iter=200)
     t0 = time.perf_counter()
-    fld.solve(delta, BOX, prm, fixed_iters=0)
-    t_setup = time.perf_counter() - t0
+    force, _ = pm.pm_forces(delta, u, pos_h, BOX, prm, OM0, A)
+    t["forces"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    fld.solve(delta, BOX, prm, fixed_iters=2)
-    t2 = time.perf_counter() - t0
-    per_pass = (t2 - t_setup) / 2.0
-    return {"value": N ** 3 / per_pass, "unit": "cells*iter/s", "cores": 1, "kind": "oracle",
-            "sample": "2 relaxation passes of the 256^3 solve (float64 NumPy, pocketfft, 1 thread; "
-                      "host has %d logical CPUs); deposit %.1f s, setup %.1f s excluded" %
-                      (os.cpu_count() or 0, t_dep, t_setup),
-            "seconds_per_pass": per_pass}
+    pm.kick_drift(pos_h, vel_h, force, A, DLNA, OM0, BOX)
+    t["kick_drift"] = time.perf_counter() - t0
+    t["solve"] = solves["%g" % tols[0]]["seconds"]
+    return t, solves
+
+
+def cpu_baseline(pos_h, vel_h, lam):
+    """The CPU oracle (float64 NumPy, pocketfft) on one PM step of the same 256^3 workload, timed on
+    the host: (i) as it stands, one thread; (ii) its transforms on all host cores (scipy.fft
+    workers).  value = N^3 x passes / step seconds, the GPU headline's unit, from variant (i)."""
+    from oracle import spectral
+    cores = os.cpu_count() or 1
+    t1, s1 = oracle_step(pos_h, vel_h, lam, [TOL])
+    step1 = sum(t1.values())
+    with spectral.fft_workers(cores):
+        tn, sn = oracle_step(pos_h, vel_h, lam, [TOL, 1e-10])
+    stepn = tn["deposit"] + tn["solve"] + tn["forces"] + tn["kick_drift"]
+    passes = s1["%g" % TOL]["passes"]
+    return {"value": N ** 3 * passes / step1, "unit": "cells*iter/s", "cores": 1, "kind": "oracle",
+            "sample": "one PM step of the benchmark's 256^3 load (deposit, solve from the linear guess to 1e-8, "
+                      "forces, kick-drift), float64 NumPy on 1 thread",
+            "cpu_model": cpu_model(), "host_logical_cpus": cores,
+            "stage_seconds": t1, "seconds_to_tol": {k: v["seconds"] for k, v in s1.items()},
+            "passes": passes,
+            "all_cores": {"value": N ** 3 * sn["%g" % TOL]["passes"] / stepn, "cores": cores,
+                          "transforms": "scipy.fft, workers = %d" % cores, "stage_seconds": tn,
+                          "seconds_to_tol": {k: v["seconds"] for k, v in sn.items()},
+                          "passes_to_tol": {k: v["passes"] for k, v in sn.items()}}}
 
 
 if __name__ == "__main__":

@@ -57,7 +57,10 @@ typedef enum { DGP_FP64 = 0, DGP_FP32 = 1 } dgp_precision;
  * the same float64 normalised-residual tolerance as DGP_FP64. */
 
 typedef enum { DGP_INIT_LINEAR = 0, DGP_INIT_ZERO = 1, DGP_INIT_WARM = 2 } dgp_init;
-typedef enum { DGP_FORCE_NLDGP = 0, DGP_FORCE_LDGP = 1, DGP_FORCE_GRH = 2 } dgp_force_mode;
+/* Force laws (Sec. IV): the full DGP equations (nlDGP), their linearised form (lDGP, Eq. LinearDGP), GR
+ * with the DGP expansion history (GRH, Eq. GRPoisson) and standard gravity with its own expansion
+ * history (GR: flat LCDM with the same Omega_m0 in the Poisson coefficient and in the kick-drift). */
+typedef enum { DGP_FORCE_NLDGP = 0, DGP_FORCE_LDGP = 1, DGP_FORCE_GRH = 2, DGP_FORCE_GR = 3 } dgp_force_mode;
 
 /* Parameters of one field solve / PM step.  dgp_params_init fills every field
  * from (Omega_m0, a); callers may then override any of them. */
@@ -158,7 +161,8 @@ int dgp_solve_field(dgp_plan* plan, const dgp_params* p, const double* delta, do
                     dgp_info* info, void* stream);
 
 /* Forces on particles from the modified Poisson equation (Eq. FullDGP1; lDGP: its linear
- * form; GRH: Eq. GRPoisson with the same background) and the spectral gradient i k phi
+ * form; GRH: Eq. GRPoisson with the same background; GR: Eq. GRPoisson with the flat LCDM
+ * background, kbar = c k/(a H_LCDM)) and the spectral gradient i k phi
  * (Sec. III A), interpolated with the CIC weights.
  * delta [N^3], u_state [N^3] (the solved u; unused for lDGP/GRH), pos [3][np].
  * force [3][np] float64 output: g = -(c/H0)^2 grad phi at each particle (H0 = 1, Mpc/h).
@@ -168,7 +172,8 @@ int dgp_pm_forces(dgp_plan* plan, const dgp_params* p, const double* delta, cons
 
 /* One PM step at scale factor p->a: deposit, field solve (u_state in/out, started as
  * p->init says), forces, CIC interpolation and a leapfrog step in ln a:
- *   vel += dlna * g / E(a);  pos += dlna * vel / (a_h^2 E(a_h)), a_h = a e^{dlna/2};
+ *   vel += dlna * g / E(a);  pos += dlna * vel / (a_h^2 E(a_h)), a_h = a e^{dlna/2}
+ * (E of the DGP background, or of flat LCDM for DGP_FORCE_GR);
  * positions wrapped into [0, L).  vel holds p = a^2 dx/dt at half steps.
  * pos, vel [3][np] (float32 if is_fp32), updated in place.
  * DGP_E_INVALID (outputs not valid) when a position is not finite. */
@@ -260,10 +265,11 @@ int dgp_timing_read(dgp_plan* plan, int cls, double* total_ms, long long* launch
 /* Multi-step PM run (Sec. III A time stepping, Sec. III D): n_steps leapfrog steps of dlna
  * starting at scale factor a_start.  Step k runs at a_k = a_start exp(k dlna) with the
  * background coefficients of params recomputed for a_k (the other fields of params are used
- * as given).  While a_k < a_switch the force law is the linearised DGP one (DGP_FORCE_LDGP, no
- * field solve, as the paper does at early times); from the first step with a_k >= a_switch on
- * it is params->force_mode, and every nonlinear solve after the first starts from the previous
- * step's field (warm start).  pos, vel, u_state as for dgp_step; info: n_steps entries (or
+ * as given).  For params->force_mode = DGP_FORCE_NLDGP: while a_k < a_switch the force law is
+ * the linearised DGP one (DGP_FORCE_LDGP, no field solve, as the paper does at early times); from
+ * the first step with a_k >= a_switch on it is the full one, and every nonlinear solve after the
+ * first starts from the previous step's field (warm start).  The other force modes (the lDGP,
+ * GRH and GR comparison runs) use their law at every step and ignore a_switch.  pos, vel, u_state as for dgp_step; info: n_steps entries (or
  * NULL).  Returns the worst step status, or a negative error (the run stops at the first). */
 int dgp_run(dgp_plan* plan, const dgp_params* params, void* pos, void* vel, int is_fp32, long long np,
             double a_start, double dlna, int n_steps, double a_switch, double* u_state, dgp_info* info,

@@ -26,6 +26,18 @@ def hubble_E(omega_m0, a):
     return 0.5 * (b + math.sqrt(b * b + 4.0 * om / a ** 3))
 
 
+def hubble_E_lcdm(omega_m0, a):
+    """E(a) of the standard-gravity comparison runs (GR with its own expansion history): flat
+    LCDM with the same Omega_m0 (Sec. III A parameters), E^2 = Om0 a^-3 + (1 - Om0)."""
+    om = float(omega_m0)
+    return math.sqrt(om / a ** 3 + (1.0 - om))
+
+
+def omega_m_lcdm(omega_m0, a):
+    """Omega_m(a) = Om0 a^-3 / E^2 of the flat LCDM background."""
+    return float(omega_m0) / a ** 3 / hubble_E_lcdm(omega_m0, a) ** 2
+
+
 def eta_of(omega_m0, a):
     """eta = r_c H (Sec. II) = E(a) / (1 - Om0)."""
     return hubble_E(omega_m0, a) / (1.0 - omega_m0)

@@ -18,17 +18,20 @@ Readings (the paper gives the equations but not these details):
 * leapfrog with momenta p = a^2 dx/dt held at half steps:
   dp/dln a = g / E(a) (kick at a_n with the full step), then
   dx/dln a = p / (a^2 E(a)) evaluated at a_{n+1/2} = a_n e^{dlna/2} (drift),
-  then positions are wrapped into [0, L).
+  then positions are wrapped into [0, L);
+* force laws: nlDGP (Eqs. FullDGP1-2), lDGP (their linear form), GRH (Eq. GRPoisson with the DGP
+  expansion history) and GR (standard gravity with its own expansion history, read as flat
+  LCDM with the same Omega_m0, in the Poisson coefficient and in the time integration).
 """
 import math
 import numpy as np
 
 from . import spectral as sp
-from .cosmology import coefficients, hubble_E, C_OVER_H0
+from .cosmology import coefficients, hubble_E, hubble_E_lcdm, omega_m_lcdm, C_OVER_H0
 from . import field as fld
 
 QBITS = 40
-FORCE_NLDGP, FORCE_LDGP, FORCE_GRH = 0, 1, 2
+FORCE_NLDGP, FORCE_LDGP, FORCE_GRH, FORCE_GR = 0, 1, 2, 3
 
 
 def _cell_and_weights(pos, n, box):
@@ -84,11 +87,17 @@ def phi_spectrum(delta, u, box, prm, omega_m0, a, mode=FORCE_NLDGP):
       -(kbar^2 + kbar/eta) phi = (3/2)((eta-1)/eta) delta - u/(2 eta) + c2 u/kbar.
     lDGP uses the linear u (Sec. II, Eq. LinearDGP is its expansion).
     GRH: Eq. GRPoisson with the DGP background, -kbar^2 phi = (3/2)((eta-1)/eta) delta.
+    GR: Eq. GRPoisson with its own (flat LCDM) background: kbar = c k/(a H_LCDM) and
+    Omega_m(a) of LCDM, -kbar^2 phi = (3/2) Omega_m(a) delta.
     k = 0 -> 0.
     """
     n = delta.shape[-1]
     c = coefficients(omega_m0, a)
     dk = sp.fft3(fld.remove_mean(delta))
+    if mode == FORCE_GR:
+        kb = np.broadcast_to(sp.kbar(n, box, C_OVER_H0 / (a * hubble_E_lcdm(omega_m0, a))), dk.shape)
+        num = 1.5 * omega_m_lcdm(omega_m0, a) * dk
+        return np.where(kb > 0, -num / np.where(kb > 0, kb * kb, 1.0), 0.0)
     kb = np.broadcast_to(sp.kbar(n, box, c.kappa), dk.shape)
     ikb = sp.inv_kbar(n, box, c.kappa)
     om = 1.5 * (c.eta - 1.0) / c.eta
@@ -133,12 +142,13 @@ def cic_interpolate(mesh, pos, box):
     return out
 
 
-def kick_drift(pos, vel, force, a, dlna, omega_m0, box):
-    """One leapfrog step in ln a (readings in the module docstring).  Returns (pos, vel)."""
+def kick_drift(pos, vel, force, a, dlna, omega_m0, box, hubble=hubble_E):
+    """One leapfrog step in ln a (readings in the module docstring); ``hubble`` is the background
+    E(a) of the run (the DGP one, or LCDM for standard gravity).  Returns (pos, vel)."""
     dt = pos.dtype
-    e_n = hubble_E(omega_m0, a)
+    e_n = hubble(omega_m0, a)
     a_half = a * math.exp(0.5 * dlna)
-    e_half = hubble_E(omega_m0, a_half)
+    e_half = hubble(omega_m0, a_half)
     kick = dlna / e_n
     drift = dlna / (a_half * a_half * e_half)
     v = np.asarray(vel, dtype=np.float64) + kick * force
@@ -166,23 +176,27 @@ def step(pos, vel, u_state, a, dlna, box, n, prm, omega_m0, mode=FORCE_NLDGP):
     else:
         u, info = u_state, None
     force, _ = pm_forces(delta, u, pos, box, prm, omega_m0, a, mode)
-    x, v = kick_drift(pos, vel, force, a, dlna, omega_m0, box)
+    x, v = kick_drift(pos, vel, force, a, dlna, omega_m0, box, hubble_E_lcdm if mode == FORCE_GR else hubble_E)
     return x, v, u, info
 
 
 def run(pos, vel, a_start, dlna, n_steps, a_switch, box, n, omega_m0, lam, tol, max_iter=100, w=1.0 / 3.0,
-        spherical=False):
+        spherical=False, mode=FORCE_NLDGP):
     """n_steps PM steps from a_start (Sec. III A time stepping; Sec. III D: the linearised DGP
     Poisson equation at early times, the full nonlinear solve from a_switch on).  Step k runs at
     a_k = a_start exp(k dlna) with the coefficients of a_k; each nonlinear solve after the first
     starts from the previous step's field.  spherical: the spherical approximation (Eq. SphPoi)
-    replaces the full solve.  Returns (pos, vel, u, [SolveInfo or None per step])."""
+    replaces the full solve.  mode other than nlDGP: every step uses that force law (the lDGP,
+    GRH and GR comparison runs; no switch).  Returns (pos, vel, u, [SolveInfo or None per step])."""
     u = None
     infos = []
     for k in range(n_steps):
         a = a_start * math.exp(k * dlna)
         prm = fld.SolveParams.from_cosmology(omega_m0, a, lam=lam, w=w, tol=tol, max_iter=max_iter)
-        if a < a_switch:
+        if mode != FORCE_NLDGP:
+            pos, vel, _, _ = step(pos, vel, None, a, dlna, box, n, prm, omega_m0, mode=mode)
+            infos.append(None)
+        elif a < a_switch:
             pos, vel, _, _ = step(pos, vel, None, a, dlna, box, n, prm, omega_m0, mode=FORCE_LDGP)
             infos.append(None)
         elif spherical:

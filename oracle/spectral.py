@@ -14,18 +14,41 @@ Conventions (readings of what the paper leaves open):
   component is 0: the mixed Hessian terms (i != j) and the gradient i k_i.
   This keeps every spectrum Hermitian, so each inverse transform is real.
 
-Transforms are numpy's rfftn / irfftn over all three axes (last axis halved).
+Transforms are numpy's rfftn / irfftn over all three axes (last axis halved).  ``fft_workers``
+switches the same transforms to scipy.fft with a number of threads (used only to time the oracle
+on all host cores; results agree to rounding).
 """
+import contextlib
+
 import numpy as np
+
+_WORKERS = None
+
+
+@contextlib.contextmanager
+def fft_workers(workers):
+    """Within the block, fft3 / ifft3 run as scipy.fft transforms on `workers` threads."""
+    global _WORKERS
+    old, _WORKERS = _WORKERS, workers
+    try:
+        yield
+    finally:
+        _WORKERS = old
 
 
 def fft3(x):
     """Forward 3D real-to-complex transform (unnormalised)."""
+    if _WORKERS:
+        import scipy.fft
+        return scipy.fft.rfftn(np.asarray(x, dtype=np.float64), axes=(-3, -2, -1), workers=_WORKERS)
     return np.fft.rfftn(np.asarray(x, dtype=np.float64), axes=(-3, -2, -1))
 
 
 def ifft3(xk, n):
     """Inverse 3D complex-to-real transform (carries 1/N^3)."""
+    if _WORKERS:
+        import scipy.fft
+        return scipy.fft.irfftn(xk, s=(n, n, n), axes=(-3, -2, -1), workers=_WORKERS)
     return np.fft.irfftn(xk, s=(n, n, n), axes=(-3, -2, -1))
 
 

@@ -9,7 +9,7 @@ DGP_OK, DGP_NOT_CONVERGED, DGP_BAD_POINTS = 0, 1, 2
 DGP_E_INVALID, DGP_E_NOMEM, DGP_E_HIP, DGP_E_UNSUPPORTED = -1, -2, -3, -4
 DGP_FP64, DGP_FP32 = 0, 1
 DGP_INIT_LINEAR, DGP_INIT_ZERO, DGP_INIT_WARM = 0, 1, 2
-DGP_FORCE_NLDGP, DGP_FORCE_LDGP, DGP_FORCE_GRH = 0, 1, 2
+DGP_FORCE_NLDGP, DGP_FORCE_LDGP, DGP_FORCE_GRH, DGP_FORCE_GR = 0, 1, 2, 3
 
 EXPORTS = (
     "dgp_params_init", "dgp_plan_create", "dgp_plan_destroy", "dgp_plan_device_bytes",

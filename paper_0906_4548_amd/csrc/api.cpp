@@ -125,6 +125,8 @@ static double hubble_E(double om0, double a) {
   return 0.5 * (b + std::sqrt(b * b + 4.0 * om0 / (a * a * a)));
 }
 static constexpr double kCOverH0 = 2997.92458;
+// flat LCDM with the same Omega_m0: the background of the standard-gravity (GR) runs
+static double hubble_E_lcdm(double om0, double a) { return std::sqrt(om0 / (a * a * a) + (1.0 - om0)); }
 
 extern "C" int dgp_params_init(dgp_params* p, double omega_m0, double a) {
   if (!p) return fail(DGP_E_INVALID, "params is NULL");
@@ -167,7 +169,7 @@ static int check_params(const dgp_params* p) {
   if (!(p->omega_relax > 0.0 && p->omega_relax <= 1.0)) return fail(DGP_E_INVALID, "omega_relax must be in (0, 1]");
   if (p->max_iter < 0 || p->max_iter >= kMaxHist - 1) return fail(DGP_E_INVALID, "max_iter must be in [0, %d)", kMaxHist - 1);
   if (p->init < 0 || p->init > 2) return fail(DGP_E_INVALID, "bad init");
-  if (p->force_mode < 0 || p->force_mode > 2) return fail(DGP_E_INVALID, "bad force_mode");
+  if (p->force_mode < 0 || p->force_mode > 3) return fail(DGP_E_INVALID, "bad force_mode");
   if (!(p->alpha > 0.0) || !(p->kappa > 0.0) || !(p->eta > 0.0)) return fail(DGP_E_INVALID, "alpha, kappa, eta must be > 0");
   return DGP_OK;
 }
@@ -783,6 +785,11 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
   const size_t fs = pl->hs, n3 = pl->n3;
   SpecCoef cf = spec_coef(pl, p);
   cf.with_phi = phi_n ? 1 : 0;
+  if (p->force_mode == DGP_FORCE_GR) {   // Eq. GRPoisson in the LCDM background: kbar = c k/(a H), (3/2) Omega_m(a)
+    const double e = hubble_E_lcdm(p->omega_m0, p->a);
+    cf.kappa = kCOverH0 / (p->a * e);
+    cf.om15 = 1.5 * p->omega_m0 / (p->a * p->a * p->a * e * e);
+  }
   const bool use_u = p->force_mode == DGP_FORCE_NLDGP;
   const int nout = phi_n ? 4 : 3;
   if (pl->precision == DGP_FP32) {
@@ -864,9 +871,10 @@ extern "C" int dgp_step(dgp_plan* pl, const dgp_params* p, void* pos, void* vel,
   }
   TRY(force_mesh(pl, p, pl->delta, u_state, nullptr, solve, s));
   const double a = p->a;
-  const double e_n = hubble_E(p->omega_m0, a);
+  double (*const hub)(double, double) = p->force_mode == DGP_FORCE_GR ? hubble_E_lcdm : hubble_E;
+  const double e_n = hub(p->omega_m0, a);
   const double a_h = a * std::exp(0.5 * dlna);
-  const double e_h = hubble_E(p->omega_m0, a_h);
+  const double e_h = hub(p->omega_m0, a_h);
   const double kick = dlna / e_n;
   const double drift = dlna / (a_h * a_h * e_h);
   {
@@ -1290,7 +1298,7 @@ extern "C" int dgp_run(dgp_plan* pl, const dgp_params* p, void* pos, void* vel, 
     q.nonlocal = p->nonlocal;
     q.check_every = p->check_every;
     q.spherical = p->spherical;
-    const bool early = a < a_switch;
+    const bool early = p->force_mode == DGP_FORCE_NLDGP && a < a_switch;
     q.force_mode = early ? DGP_FORCE_LDGP : p->force_mode;
     q.init = (q.force_mode == DGP_FORCE_NLDGP && solved) ? DGP_INIT_WARM : p->init;
     dgp_info one{};

@@ -23,7 +23,7 @@ enum SpecMode : int {
   SPEC_INV_ONLY = 9,  // inverse axis-2 transform only, times 1/N^3 (spectrum import)
 };
 
-enum ForceMode : int { FORCE_NLDGP = 0, FORCE_LDGP = 1, FORCE_GRH = 2 };
+enum ForceMode : int { FORCE_NLDGP = 0, FORCE_LDGP = 1, FORCE_GRH = 2, FORCE_GR = 3 };
 
 // Coefficients consumed by the spectral kernels (all double; fp32 kernels round at use).
 struct SpecCoef {

@@ -476,7 +476,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
             // phi(k) from the modified Poisson equation (or its linear / GR forms)
             const double dr = double(v[q].x), di = double(v[q].y);
             double nr, ni, den;
-            if (cf.force_mode == FORCE_GRH) {
+            if (cf.force_mode == FORCE_GRH || cf.force_mode == FORCE_GR) {   // Eq. GRPoisson (kappa, om15 of the run's background)
               nr = cf.om15 * dr; ni = cf.om15 * di; den = kb * kb;
             } else {
               double ur, ui;

@@ -14,7 +14,8 @@ from ._lib import Params, Info, check
 
 FP64, FP32 = _lib.DGP_FP64, _lib.DGP_FP32
 INIT_LINEAR, INIT_ZERO, INIT_WARM = _lib.DGP_INIT_LINEAR, _lib.DGP_INIT_ZERO, _lib.DGP_INIT_WARM
-FORCE_NLDGP, FORCE_LDGP, FORCE_GRH = _lib.DGP_FORCE_NLDGP, _lib.DGP_FORCE_LDGP, _lib.DGP_FORCE_GRH
+FORCE_NLDGP, FORCE_LDGP, FORCE_GRH, FORCE_GR = (_lib.DGP_FORCE_NLDGP, _lib.DGP_FORCE_LDGP, _lib.DGP_FORCE_GRH,
+                                              _lib.DGP_FORCE_GR)
 
 
 def params(omega_m0=0.27, a=0.5, **overrides):

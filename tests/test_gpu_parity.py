@@ -250,7 +250,7 @@ def test_deposit_binned_bit_exact(dgp, case):
         assert np.array_equal(g.cpu().numpy().reshape(n, n, n), grid_ref)
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_pm_forces(dgp, mode):
     say("forces", mode)
     n, box = 32, 64.0
@@ -435,6 +435,49 @@ def test_run_against_oracle(dgp, prec):
         dx_ref = (x_ref - pos + box / 2) % box - box / 2
         assert rel_l2(dx, dx_ref) <= tol
         assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= tol
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_comparison_runs_against_oracle(dgp, mode):
+    """The lDGP, GRH and GR comparison runs (Sec. IV): dgp_run with that force law at every step
+    (GR in its own LCDM background, kick-drift included) against the oracle's driver."""
+    say("comparison run", mode)
+    n, box, pos, vel, a0, dlna, lam = _run_case()
+    x_ref, v_ref, _, infos = pm.run(pos, vel, a0, dlna, 3, 0.47, box, n, OM0, lam, 1e-11, mode=mode)
+    with dgp.Plan(n, box) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, steps = plan.run(dgp.params(OM0, a0, lam=lam, tol=1e-11, max_iter=100, force_mode=mode), tp, tv, u, a0,
+                             dlna, 3, 0.47)
+        assert st == 0 and all(s["passes"] == 0 for s in steps)
+        dx = (tp.cpu().numpy() - pos + box / 2) % box - box / 2
+        dx_ref = (x_ref - pos + box / 2) % box - box / 2
+        assert rel_l2(dx, dx_ref) <= 1e-10
+        assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= 1e-10
+
+
+@pytest.mark.parametrize("w", [0.0, 0.25, 1.0 / 3.0, 0.5, 0.8])
+def test_w_scan_fig3(dgp, w):
+    """The w-scan of Sec. III C (Fig. 3) on the z = 24 particle density of the oracle's Fig. 3 test
+    (lam = 1, the same linear solution for every w, 20 updates): residual and bad-fraction history
+    of every update against the oracle, including the w = 0 run through its bad points."""
+    say("w scan", w)
+    from tests.test_oracle_pins import _fig3_delta
+    delta = _fig3_delta()
+    n, box, k = 64, 16.0, 20
+    prm = fld.SolveParams.from_cosmology(OM0, 1 / 25, lam=1.0, w=w)
+    u_ref, iref = fld.solve(delta, box, prm, fixed_iters=k)
+    with dgp.Plan(n, box) as plan:
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(dgp.params(OM0, 1 / 25, lam=1.0, w=w, tol=-1.0, max_iter=k), to_dev(delta), u)
+        assert st == 0 and info[0]["iters"] == k
+        hist, bad = plan.history()
+        href = np.asarray(iref.history)
+        assert len(hist) == k + 1
+        # relative, down to an absolute floor: r near 1e-10 is a mean of float64 cancellations
+        assert np.all(np.abs(hist - href) <= (1e-9 if w > 0 else 1e-7) * href + 1e-14)
+        assert np.array_equal(bad[:k] * n ** 3, np.asarray(iref.bad_history) * n ** 3)
+        assert rel_l2(u.cpu().numpy().reshape(n, n, n), u_ref) <= (1e-10 if w > 0 else 1e-7)
 
 
 def test_spherical_mode(dgp):

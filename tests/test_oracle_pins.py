@@ -89,6 +89,18 @@ def test_fft_matches_bruteforce_dft_8():
     assert np.max(np.abs(back - x)) < 1e-14
 
 
+def test_threaded_transforms_agree():
+    """The all-core timing variant runs the same transforms through scipy.fft: equal to rounding."""
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((16, 16, 16))
+    a = sp.fft3(x)
+    with sp.fft_workers(4):
+        b = sp.fft3(x)
+        xb = sp.ifft3(b, 16)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+    assert np.max(np.abs(xb - sp.ifft3(a, 16))) < 1e-14
+
+
 def test_parseval():
     rng = np.random.default_rng(1)
     x = rng.standard_normal((16, 16, 16))
@@ -486,34 +498,67 @@ def test_plane_wave_potentials_closed_form():
         assert np.max(np.abs(g[1:])) < 1e-12 * np.max(np.abs(want))
 
 
-def _exact_trajectory(x0, p0, g, s0, s1, omega_m0):
+def _exact_trajectory(x0, p0, g, s0, s1, omega_m0, hubble=None):
     """x(s1), p(s1) of dp/dln a = g / E(a), dx/dln a = p / (a^2 E(a)) (Sec. III A equations of motion
     in ln a with p = a^2 dx/dt, H0 = 1) from (x0, p0) at s0 = ln a0: an adaptive high-order ODE
     integration, independent of any leapfrog."""
     from scipy.integrate import solve_ivp
 
+    hub = hubble or cos.hubble_E
+
     def rhs(s, y):
         a = math.exp(s)
-        e = cos.hubble_E(omega_m0, a)
+        e = hub(omega_m0, a)
         return [y[1] / (a * a * e), g / e]
 
     sol = solve_ivp(rhs, (s0, s1), [x0, p0], method="DOP853", rtol=1e-13, atol=1e-15)
     return sol.y[0, -1], sol.y[1, -1]
 
 
-def _leapfrog_error(dlna, n_steps, a0=0.5, x0=10.0, p0=3.0, g=-40.0):
+def _leapfrog_error(dlna, n_steps, a0=0.5, x0=10.0, p0=3.0, g=-40.0, hubble=None):
     """Global position error of n_steps oracle kick-drift steps against the exact trajectory.
     The leapfrog holds momenta at half steps: it starts from the exact p at ln a0 - dlna/2."""
     s0 = math.log(a0)
-    _, p_half = _exact_trajectory(x0, p0, g, s0, s0 - 0.5 * dlna, OM0)
+    _, p_half = _exact_trajectory(x0, p0, g, s0, s0 - 0.5 * dlna, OM0, hubble)
     box = 1e9   # no wrap
     x = np.array([[x0]])
     v = np.array([[p_half]])
     f = np.array([[g]])
     for k in range(n_steps):
-        x, v = pm.kick_drift(x, v, f, a0 * math.exp(k * dlna), dlna, OM0, box)
-    x_exact, _ = _exact_trajectory(x0, p0, g, s0, s0 + n_steps * dlna, OM0)
+        if hubble is None:
+            x, v = pm.kick_drift(x, v, f, a0 * math.exp(k * dlna), dlna, OM0, box)
+        else:
+            x, v = pm.kick_drift(x, v, f, a0 * math.exp(k * dlna), dlna, OM0, box, hubble)
+    x_exact, _ = _exact_trajectory(x0, p0, g, s0, s0 + n_steps * dlna, OM0, hubble)
     return abs(float(x[0, 0]) - x_exact)
+
+
+def test_lcdm_background_closed_form():
+    """Standard-gravity runs use flat LCDM with the same Omega_m0: E(1) = 1, E^2 = Om0 a^-3 + 1 - Om0,
+    and Omega_m(a) = Om0 a^-3 / E^2 tends to 1 at early times."""
+    for a in (0.02, 0.1, 0.5, 1.0):
+        e = cos.hubble_E_lcdm(OM0, a)
+        assert abs(e * e - (OM0 / a ** 3 + 1 - OM0)) < 1e-12 * e * e
+        assert abs(cos.omega_m_lcdm(OM0, a) * e * e * a ** 3 - OM0) < 1e-14
+    assert cos.hubble_E_lcdm(OM0, 1.0) == 1.0
+    a = 0.02
+    assert abs((1 - cos.omega_m_lcdm(OM0, a)) - (1 - OM0) * a ** 3 / (OM0 + (1 - OM0) * a ** 3)) < 1e-15
+
+
+def test_gr_poisson_plane_wave_closed_form():
+    """Eq. GRPoisson in comoving units (lengths Mpc/h, c = 1, H0 = 1/(c/H0)):
+    lap phi = 4 pi G a^2 rho_m delta = (3/2) Om0 H0^2 delta / a, independent of the expansion rate.
+    For delta = eps cos(k0 x): phi = -(3/2) Om0 eps cos(k0 x) / (a (c/H0)^2 k0^2) with either
+    background, so GR (LCDM background) and GRH (DGP background) share the force of a given delta."""
+    n, box, a = 16, 256.0, 0.5
+    prm = params(a=a)
+    x = np.arange(n) * box / n
+    k0, amp = 2 * np.pi * 3 / box, 0.04
+    delta = amp * np.cos(k0 * x)[None, :, None] * np.ones((n, n, n))
+    want = -1.5 * OM0 * amp / (a * 2997.92458 ** 2 * k0 ** 2) * np.cos(k0 * x)[None, :, None]
+    for mode in (pm.FORCE_GR, pm.FORCE_GRH):
+        phi = sp.ifft3(pm.phi_spectrum(delta, None, box, prm, OM0, a, mode), n)
+        assert np.max(np.abs(phi - want)) < 1e-12 * np.max(np.abs(want))
 
 
 def test_kick_drift_is_a_second_order_leapfrog():
@@ -526,6 +571,29 @@ def test_kick_drift_is_a_second_order_leapfrog():
     for coarse, fine in zip(errs, errs[1:]):
         assert 3.6 < coarse / fine < 4.4, errs
     assert errs[-1] < 1e-3
+    # the standard-gravity runs integrate in their own (LCDM) background
+    errs = [_leapfrog_error(span / k, k, hubble=cos.hubble_E_lcdm) for k in (8, 16, 32)]
+    for coarse, fine in zip(errs, errs[1:]):
+        assert 3.6 < coarse / fine < 4.4, errs
+
+
+def test_gr_step_integrates_in_the_lcdm_background():
+    """A GR step (Sec. III A with standard gravity) kicks and drifts with E_LCDM; GRH with the DGP E:
+    with the same force the two differ exactly by the background factors."""
+    n, box, a, dlna = 8, 16.0, 0.5, 0.01
+    pos, psi = inputs.zeldovich_load(n, box, 3, rms_disp=0.5)
+    vel = 0.2 * psi
+    prm = params(a=a)
+    x_gr, v_gr, _, _ = pm.step(pos, vel, None, a, dlna, box, n, prm, OM0, mode=pm.FORCE_GR)
+    x_grh, v_grh, _, _ = pm.step(pos, vel, None, a, dlna, box, n, prm, OM0, mode=pm.FORCE_GRH)
+    _, delta = pm.deposit(pos, n, box)
+    f, _ = pm.pm_forces(delta, None, pos, box, prm, OM0, a, pm.FORCE_GRH)
+    for hub, v, x in ((cos.hubble_E_lcdm, v_gr, x_gr), (cos.hubble_E, v_grh, x_grh)):
+        ah = a * math.exp(dlna / 2)
+        vv = vel + dlna * f / hub(OM0, a)
+        xx = np.mod(pos + dlna * vv / (ah * ah * hub(OM0, ah)), box)
+        assert np.allclose(v, vv, rtol=1e-12, atol=1e-14) and np.allclose(x, xx, rtol=0, atol=1e-11)
+    assert np.max(np.abs(v_gr - v_grh)) > 1e-3 * np.max(np.abs(v_grh - vel))
 
 
 def test_kick_drift_wraps_into_box():
@@ -731,3 +799,40 @@ def test_pc_over_pm_is_one_in_the_linear_local_limit():
     dg = diagnostics.delta_gradc(u, box, prm)
     pc, _, _ = power.power_spectrum(fld.c_from_u(u, box, prm), box)
     assert np.allclose(dg, 4 * np.pi * kc ** 5 * pc)
+
+
+def _fig3_delta(nside=32, box=16.0):
+    """A z = 24 particle density: a seeded Zel'dovich load (P ~ k^-1.5 exp(-k^2/k_c^2), k_c = 4 h/Mpc,
+    rms displacement 0.15 Mpc/h) of nside^3 particles deposited on a (2 nside)^3 mesh, one particle
+    per 8 cells as in the paper's runs, with cells of 0.25 Mpc/h (the Fig. 3 mesh spacing)."""
+    pos, _ = inputs.zeldovich_load(nside, box, 24, slope=-1.5, kc=4.0, rms_disp=0.15)
+    _, delta = pm.deposit(pos, 2 * nside, box)
+    return delta
+
+
+def test_w_scan_reproduces_fig3_behaviour():
+    """Sec. III C, Fig. 3 discussion (z = 24, lam = 1, all w from the same linear solution): the same
+    initial residual for every w; for w = 0 bad points appear and the residual decreases for a
+    few iterations, then bounces back and increases; for w = 0.25, 1/3, 0.5 and 0.8 the bad
+    fraction stays zero; 0.5 converges slightly faster than 1/3, 0.25 slower than both, and 0.8
+    much slower.  (The paper's w = 0.25 is Eq. ZeroDis at z = 24.)"""
+    delta = _fig3_delta()
+    box, k = 16.0, 20
+    hist = {}
+    for w in (0.0, 0.25, 1 / 3, 0.5, 0.8):
+        prm = fld.SolveParams.from_cosmology(OM0, 1 / 25, lam=1.0, w=w)
+        _, info = fld.solve(delta, box, prm, fixed_iters=k)
+        hist[w] = (np.array(info.history), np.array(info.bad_history))
+    r0 = hist[0.0][0][0]
+    assert all(abs(h[0] / r0 - 1) < 1e-14 for h, _ in hist.values())
+    r, bad = hist[0.0]
+    assert bad.max() > 0.01
+    m = int(np.argmin(r))
+    assert 0 < m < k // 2 and r[-1] > 1.2 * r[m] and np.all(np.diff(r[m:]) > -0.05 * r[m:-1])
+    for w in (0.25, 1 / 3, 0.5, 0.8):
+        r, bad = hist[w]
+        assert np.all(bad == 0) and np.all(np.diff(r) < 0)
+    last = {w: hist[w][0][-1] for w in hist}
+    assert last[0.5] < last[1 / 3] < last[0.25] < last[0.8]
+    assert last[1 / 3] / last[0.5] < 1e3 and last[0.8] / last[1 / 3] > 1e3
+    assert round(cos.w_zero_discriminant(OM0, 1 / 25), 2) == 0.25
