@@ -33,13 +33,13 @@ const cx<T>* twiddles(int n);
 #define DGP_PLAN_RELAX 2
 #endif
 #ifndef DGP_PLAN_RELAX_F32
-#define DGP_PLAN_RELAX_F32 2
+#define DGP_PLAN_RELAX_F32 0
 #endif
 #ifndef DGP_RELAX_F32ACC
 #define DGP_RELAX_F32ACC 1
 #endif
 #ifndef DGP_RELAX_TP_F32
-#define DGP_RELAX_TP_F32 0
+#define DGP_RELAX_TP_F32 8
 #endif
 #ifndef DGP_RELAX_MINW_F32
 #define DGP_RELAX_MINW_F32 1
