@@ -11,7 +11,8 @@ Lagrangian blocks of 8^3 (a spatially coherent order, as a PM code keeps them).
 
 Other modes:
   --probe                 a short run for hardware-counter passes (two precision-form
-                          steps plus a plain 512 MiB device copy for calibration)
+                          steps plus a plain 512 MiB device copy for calibration);
+                          with --stages: the same at 512^3 (one precision-form step)
   --pmc-summary F W       turn the counter CSVs of two such passes (FETCH_SIZE, then
                           WRITE_SIZE) into the traffic summary kept under profiles/
   --trace-summary T       per-kernel duration table of a rocprofv3 kernel trace
@@ -97,7 +98,7 @@ def read_counters(path):
     return out
 
 
-def pmc_summary(fetch_csv, write_csv):
+def pmc_summary(fetch_csv, write_csv, mesh=256):
     """Markdown summary of HBM traffic per dispatch, calibrated on the probe's plain copy."""
     fetch, write = read_counters(fetch_csv), read_counters(write_csv)
     copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
@@ -123,17 +124,18 @@ def pmc_summary(fetch_csv, write_csv):
         rows[name] = {"fetch_bytes": f, "write_bytes": w, "dispatches": len(fetch[name]), "working": len(fv)}
         table.append("| `%s` | %d | %d | %.1f | %s |" % (name, len(fetch[name]), len(fv), f / 2 ** 20,
                                                          "%.1f" % (w / 2 ** 20) if w is not None else "-"))
+    probe = "--probe" if mesh == 256 else "--stages --probe"
     lines = [
-        "# HBM traffic per dispatch: PM step at 256^3 (FETCH_SIZE / WRITE_SIZE, calibrated)",
+        "# HBM traffic per dispatch: PM step at %d^3 (FETCH_SIZE / WRITE_SIZE, calibrated)" % mesh,
         "",
         "Commands (repository root `$R`, any output directory `$OUT`, one MI355X; one counter per pass):",
         "",
         "    cd /tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d $OUT/pmc_fetch -o run -- "
-        "python3 $R/bench.py --probe",
+        "python3 $R/bench.py %s" % probe,
         "    cd /tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d $OUT/pmc_write -o run -- "
-        "python3 $R/bench.py --probe",
+        "python3 $R/bench.py %s" % probe,
         "    python3 bench.py --pmc-summary <pmc_fetch>/run_counter_collection.csv "
-        "<pmc_write>/run_counter_collection.csv",
+        "<pmc_write>/run_counter_collection.csv%s" % ("" if mesh == 256 else " --pmc-mesh %d" % mesh),
         "",
         "Calibration: the probe's plain copy `%s` moves %d MiB each way; its raw counters read "
         "%.1f MiB fetched and %.1f MiB written, so fetch values are scaled by %.3f and write values by %.3f."
@@ -230,6 +232,21 @@ def stages_512(args, torch, dgp, inputs, dev):
         lam = RNL * prm0.alpha / float(ulin.abs().max())
     del delta, ulin
     torch.cuda.empty_cache()
+    if args.probe:   # counter pass at 512^3: calibration copy, one warm-up and one timed precision-form step
+        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        plan = dgp.Plan(n, box, precision=dgp.FP32)
+        prm = dgp.params(OM0, A, lam=lam, tol=TOL, max_iter=200, init=dgp.INIT_LINEAR, check_every=8)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            plan.step(prm, pos0, vel0, u, DLNA)
+        torch.cuda.synchronize()
+        plan.close()
+        print("probe done", file=sys.stderr, flush=True)
+        return
     out = {"mode": "stages", "config": {"workload": "Zel'dovich PM step, 512^3 mesh, 512^3 float32 particles, "
                                                     "box 1024 Mpc/h, z=1, r_nl=%.2f, tol 1e-8" % RNL,
                                         "mesh": n, "particles": npart, "lambda": lam, "steps": steps}}
@@ -339,6 +356,7 @@ def main():
     ap.add_argument("--probe", action="store_true", help="short run for hardware-counter passes")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the calibrated traffic summary from two counter passes to stdout")
+    ap.add_argument("--pmc-mesh", type=int, default=256, help="mesh size the counter passes ran at")
     ap.add_argument("--stages", action="store_true",
                     help="per-stage times of a 512^3 PM step with 512^3 float32 particles, both forms")
     ap.add_argument("--wscan", action="store_true", help="the w-scan of Fig. 3 at the paper's size")
@@ -346,7 +364,7 @@ def main():
                     help="write a per-kernel duration table from a rocprofv3 kernel trace to stdout")
     args = ap.parse_args()
     if args.pmc_summary:
-        print(pmc_summary(*args.pmc_summary))
+        print(pmc_summary(*args.pmc_summary, mesh=args.pmc_mesh))
         return
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
