@@ -71,7 +71,7 @@ template const cx<double>* twiddles<double>(int);
 template const cx<float>* twiddles<float>(int);
 }  // namespace dgp
 
-// exp(-2 pi i m / n) in double; cos/sin of angles reduced to the first octant by symmetry
+// exp(-2 pi i m / n) in double: long-double cos/sin of 2 pi m / n, exact values at the quarter points
 static void twiddle_values(int n, std::vector<double>& re, std::vector<double>& im) {
   re.resize(n);
   im.resize(n);

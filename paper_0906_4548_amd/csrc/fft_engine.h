@@ -295,17 +295,13 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // LDS accessor for strided columns: element e of column c at base[e * C + c].
-// WAVE: the transform's threads all belong to one wavefront (wave-local ordering suffices).
-template <typename T, int C, bool WAVE = false>
+template <typename T, int C>
 struct LdsCol {
   cx<T>* base;
   int c;
   __device__ __forceinline__ cx<T> load(int e) const { return base[e * C + c]; }
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[e * C + c] = v; }
-  __device__ __forceinline__ void sync() const {
-    if constexpr (WAVE) wave_sync();
-    else lds_barrier();
-  }
+  __device__ __forceinline__ void sync() const { lds_barrier(); }
 };
 
 // LDS accessor for contiguous rows: element e of row c at base[c * (N + N/16) + e + e/16].

@@ -184,45 +184,6 @@ k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const So
   for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
 }
 
-// Axis 1 with every column transform inside one wavefront: a wave owns WC = 64/T adjacent
-// columns (T lanes each), so radix-stage exchanges need no workgroup barrier; four waves per
-// workgroup cover 4*WC adjacent columns of the same rows.
-#ifndef DGP_P2_WAVE
-#define DGP_P2_WAVE 0
-#endif
-template <typename T, int N>
-struct WaveCol {
-  using P = Plan<N>;
-  static constexpr int R = P::R;
-  static constexpr int kT = N / R;
-  static constexpr int kWC = (64 / kT > 0) ? 64 / kT : 1;     // columns per wave
-  static constexpr int kWaves = 4;
-  static constexpr int kTY = kWC * kWaves;                      // columns per workgroup
-  static constexpr bool kOk = (kT <= 64) && (kTY <= N);
-};
-
-template <typename T, int N, int DIR>
-__global__ void __launch_bounds__(256)
-k_p2_wave(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const SolveCtl* __restrict__ ctl) {
-  using W = WaveCol<T, N>;
-  using P = typename W::P;
-  constexpr int R = W::R, TT = W::kT, WC = W::kWC, H = N / 2 + 1;
-  const int fb = blockIdx.z;
-  if (batch_done(ctl, fb % batch)) return;
-  const int k0 = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int c = lane % WC, t = lane / WC;
-  __shared__ cx<T> lds[W::kWaves * N * WC];
-  cx<T>* base = data + ((size_t)fb * H + k0) * N * N + blockIdx.x * W::kTY + wave * WC + c;
-  cx<T> v[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = base[(size_t)(t + q * TT) * N];
-  LdsCol<T, WC, true> L{lds + wave * N * WC, c};
-  fft<T, N, P, DIR>(v, tw, L, t);
-#pragma unroll
-  for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
-}
-
 // ------------------------------------------------------------------ axis 2 with spectral multipliers
 struct Mode3 {
   int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
@@ -528,13 +489,6 @@ static void p1_inv_n(const cx<T>* in, T* out, int batch, const SolveCtl* ctl, co
 }
 template <typename T, int N>
 static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
-  if constexpr (DGP_P2_WAVE && WaveCol<T, N>::kOk && N >= 64) {
-    using W = WaveCol<T, N>;
-    dim3 grid(N / W::kTY, N / 2 + 1, nf * batch);
-    if (dir < 0) hipLaunchKernelGGL((k_p2_wave<T, N, -1>), grid, dim3(256), 0, s, data, batch, tw, ctl);
-    else hipLaunchKernelGGL((k_p2_wave<T, N, +1>), grid, dim3(256), 0, s, data, batch, tw, ctl);
-    return;
-  }
   using G = ColTile<T, N, Geo<T, N>::P2::R>;
   dim3 grid(N / G::kTY, N / 2 + 1, nf * batch);
   if (dir < 0) hipLaunchKernelGGL((k_p2<T, N, -1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);

@@ -44,6 +44,18 @@ const cx<T>* twiddles(int n);
 #ifndef DGP_RELAX_MINW_F32
 #define DGP_RELAX_MINW_F32 1
 #endif
+// smallest N whose float32 relaxation kernel pairs its lanes: the two threads whose transform
+// elements e and N - e share a spectral row sit in one wavefront and load that row in the same
+// instruction (one request instead of two)
+#ifndef DGP_RELAX_PAIRED_MIN
+#define DGP_RELAX_PAIRED_MIN 256
+#endif
+// smallest N whose float32 relaxation kernel re-derives its lane indices at every field, so that
+// the per-lane addresses built from them are not held across the field loop (at N = 512 the
+// 1024-thread workgroup leaves 128 VGPRs per lane)
+#ifndef DGP_RELAX_REMAT_MIN
+#define DGP_RELAX_REMAT_MIN 512
+#endif
 
 // axis-0 tile of the relaxation kernel: AxisTile with an optional number of column pairs
 template <typename T, int N, int R, int TPSET>
@@ -68,6 +80,9 @@ struct RelaxGeo {
   // accumulators of the float32 form (sum h^2 and -(h00 + h11)): float32 or float64; the
   // residual, discriminant and root are float64 either way
   using Acc = typename std::conditional<DGP_RELAX_F32ACC, float, double>::type;
+  // lane order of the paired loads (needs an even number of transform positions per wavefront)
+  static constexpr bool kPaired = N >= DGP_RELAX_PAIRED_MIN && (64 / G::kTP) % 2 == 0;
+  static constexpr bool kRemat = N >= DGP_RELAX_REMAT_MIN;
 };
 
 // sum over the W lanes of a wavefront segment (butterfly order, deterministic)
@@ -167,30 +182,42 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   const int cur = ctl[b].cur, nxt = ctl[b].out;
   int tile, i1;
   xcd_tile(tile, i1);
-  const int c = threadIdx.x % TP, t = threadIdx.x / TP;
+  int c = threadIdx.x % TP;
+  // transform element index t of this thread.  Paired order: positions g = 0, 1 take t = 0 and
+  // TT/2 (their own partners), then g = 2k, 2k + 1 take t = k and TT - k, so a wavefront (64/TP
+  // consecutive positions, an even count) holds both threads of every pair; elements e = t + q TT
+  // and N - e = (TT - t) + (R - 1 - q) TT read the same spectral row
+  const int g = threadIdx.x / TP;
+  constexpr bool PAIRED = RG::kPaired;
+  int t = !PAIRED ? g : g < 2 ? g * (TT / 2) : (g & 1) ? TT - (g >> 1) : (g >> 1);
   const int i2 = (tile * TP + c) * 2;
   __shared__ cx<T> lds[N * TP];
   __shared__ double red[(G::kThreads + 63) / 64];
   __shared__ int redi[(G::kThreads + 63) / 64];
-  LdsCol<T, TP> L{lds, c};
   // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
   // cached global loads at every stage
   __shared__ cx<T> twl[N];
   for (int i = threadIdx.x; i < N; i += G::kThreads) twl[i] = tw[i];
 
   const size_t col = (size_t)b * H * N * N + (size_t)i1 * N + i2;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const size_t col0 = (size_t)b * H * N * N + (size_t)i1 * N + (size_t)tile * TP * 2;
   // element q of thread t is row e = t + q TT of the Hermitian-extended column pair; rows e > N/2
   // come from row N - e (conjugated when used); streaming loads (the last use of these spectra in
-  // the pass)
+  // the pass).  With paired lanes, threads t > TT/2 load their elements in reverse slot order, so
+  // that slot q of both threads of a pair addresses the same row.
   cx<T> pd[R][2];
+  // (a workgroup-uniform base plus a 32-bit lane offset: one register per address)
+  static_assert((size_t)(N / 2 + 1) * N * N * sizeof(cx<T>) < (size_t(1) << 32), "32-bit row offsets");
   auto fetch_direct = [&](int f) {
-    const cx<T>* src = spec6 + f * fstride + col;
+    const char* src = reinterpret_cast<const char*>(spec6 + f * fstride + col0);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int e = t + q * TT;
-      const int r = e <= N / 2 ? e : N - e;
-      typedef float f4 __attribute__((ext_vector_type(4)));
-      const f4 x = __builtin_nontemporal_load(reinterpret_cast<const f4*>(src + (size_t)r * N * N));
+    for (int q = 0; q < R; ++q) {   // slot q holds element R - 1 - q when rev
+      const bool rev = PAIRED && t > TT / 2;
+      const int e = t + (rev ? R - 1 - q : q) * TT;
+      const unsigned r = e <= N / 2 ? e : N - e;
+      const f4* a = reinterpret_cast<const f4*>(src + (r * unsigned(N * N) + 2u * c) * unsigned(sizeof(cx<T>)));
+      const f4 x = __builtin_nontemporal_load(a);
       pd[q][0] = mk(T(x.x), T(x.y));
       pd[q][1] = mk(T(x.z), T(x.w));
     }
@@ -199,15 +226,15 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 
   Acc s2[R][2], h22[R][2];
   cx<T> v[R];
-  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
-  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
   cx<T> up[R], spv[R];
 #pragma unroll 1
   for (int f = 0; f < 6; ++f) {
+    if constexpr (RG::kRemat) asm volatile("" : "+v"(t), "+v"(c));   // opaque: recomputed per field
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int e = t + q * TT;
-      cx<T> xa = pd[q][0], xb = pd[q][1];
+      const bool rev = PAIRED && t > TT / 2;
+      cx<T> xa = rev ? pd[R - 1 - q][0] : pd[q][0], xb = rev ? pd[R - 1 - q][1] : pd[q][1];
       if (e > N / 2) {
         xa = conjg(xa);
         xb = conjg(xb);
@@ -216,7 +243,10 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       v[q] = mk(xa.x - xb.y, xa.y + xb.x);   // x_a + i x_b
     }
     if (f < 5) fetch_direct(f + 1);
-    fft<T, N, P, +1>(v, twl, L, t);
+    {
+      LdsCol<T, TP> L{lds, c};
+      fft<T, N, P, +1>(v, twl, L, t);
+    }
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -238,7 +268,9 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
       }
     }
   }
-  // pointwise residual and update; v holds Nf
+  // pointwise residual and update; v holds Nf (field addresses formed after the field loop)
+  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
   const PointCoef pc = point_coef(cfg, mean_u[b]);
   T* uout = ubuf + ((size_t)nxt * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
   double abs_r = 0.0;
@@ -259,7 +291,10 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     v[q] = o;
   }
   // forward axis-0 transform of u^(n+1)
-  fft<T, N, P, -1>(v, twl, L, t);
+  {
+    LdsCol<T, TP> L{lds, c};
+    fft<T, N, P, -1>(v, twl, L, t);
+  }
   lds_barrier();
 #pragma unroll
   for (int q = 0; q < R; ++q) lds[(t + q * TT) * TP + c] = v[q];
@@ -308,6 +343,10 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 #ifndef DGP_RELAXW_MINW_F64
 #define DGP_RELAXW_MINW_F64 3
 #endif
+// smallest N whose float64 relaxation kernel reads its twiddles from LDS
+#ifndef DGP_RELAXW_TWLDS_MIN
+#define DGP_RELAXW_TWLDS_MIN 512
+#endif
 
 template <typename T, int N>
 struct RelaxWGeo {
@@ -320,7 +359,11 @@ struct RelaxWGeo {
   static constexpr int kTPSet = kWide ? 8 : DGP_RELAXW_TP_F64;
   static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
   static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
-  static constexpr int kMinWaves = DGP_RELAXW_MINW_F64;
+  static constexpr int kMinWaves = kWide ? 2 : DGP_RELAXW_MINW_F64;   // the LDS tile allows one workgroup per CU from N = 512
+  // twiddles from an LDS copy: held in registers, the loop-invariant twiddles of the six
+  // inverse transforms would need 56 VGPRs across the field loop at N = 512, where the kernel
+  // already uses all 256 of a two-waves-per-SIMD allocation
+  static constexpr bool kTwLds = N >= DGP_RELAXW_TWLDS_MIN;
   static_assert(kT <= 64 && 64 % kT == 0, "a transform must stay inside one wavefront");
   static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
   static constexpr int kTile = H * kSP;
@@ -361,6 +404,12 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   __shared__ cx<T> lds[2 * W::kTile];
   __shared__ double redd[W::kWaves];
   __shared__ int redi[W::kWaves];
+  __shared__ cx<T> twl[W::kTwLds ? N : 1];
+  const cx<T>* twp = tw;
+  if constexpr (W::kTwLds) {
+    for (int i = threadIdx.x; i < N; i += NT) twl[i] = tw[i];   // ordered by the first field's barrier
+    twp = twl;
+  }
 
   const size_t col0 = (size_t)b * H * NN + (size_t)i1 * N + i2;
   cx<T> pf[NPF][2];
@@ -391,8 +440,6 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   };
   fetch(0);
 
-  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
-  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
   double s2[R][2], h22[R][2];
   cx<T> v[R], up[R], spv[R];
 #pragma unroll 1
@@ -416,7 +463,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
     }
     if (f < 5) fetch(f + 1);
     LdsPair<T, SP> X{buf, c};
-    fft<T, N, P, +1>(v, tw, X, t);
+    fft<T, N, P, +1>(v, twp, X, t);
     if (f < 5) {
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -438,7 +485,11 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
       }
     }
   }
-  // pointwise residual and update (v holds Nf); u^(n+1) is staged in tile 0 (free since the last barrier)
+  // pointwise residual and update (v holds Nf); u^(n+1) is staged in tile 0 (free since the last barrier).
+  // The field addresses are formed here, after the field loop, so that they are not held in
+  // registers across it.
+  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
+  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
   const PointCoef pc = point_coef(cfg, mean_u[b]);
   T* ust = reinterpret_cast<T*>(lds);
   double abs_r = 0.0;
@@ -462,7 +513,7 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   // forward axis-0 transform of u^(n+1), exchanges in the transform's own columns of tile 1
   {
     LdsPair<T, SP> X{lds + W::kTile, c};
-    fft<T, N, P, -1>(v, tw, X, t);
+    fft<T, N, P, -1>(v, twp, X, t);
   }
   abs_r = wave_sum<W::kWidth>(abs_r);
   nbad = wave_sum<W::kWidth>(nbad);
