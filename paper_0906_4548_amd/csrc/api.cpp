@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -213,8 +214,11 @@ struct dgp_plan {
   double* bin_partial = nullptr;
   double* bin_host = nullptr;        // pinned
   // adjoint (allocated on first use)
-  double* adj = nullptr;             // [15][B][n3]
+  double* adj = nullptr;             // [9][B][n3]
   double* adj_red = nullptr;
+  double* adj_vec = nullptr;         // [B] <h22 mu> of the current multipliers
+  SolveCtl* adj_ctl = nullptr;       // device [B]
+  SolveCtl* adj_ctl_host = nullptr;  // pinned [B]
   // non-finite particle flag (device, one 8-byte slot) and its pinned host copy; fixed-point
   // scale state of the interpolation adjoint
   int* flag = nullptr;
@@ -1095,12 +1099,25 @@ extern "C" int dgp_fft_inverse(dgp_plan* pl, const double* spectrum, double* fie
 int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const double* u_star, const double* grad_u,
                   double* grad_delta, dgp_info* info, hipStream_t s);
 
-// float64 work fields of the adjoint and the diagnostics, allocated on first use: [15][B][n3]
+// float64 work fields of the adjoint and the diagnostics, allocated on first use: [9][B][n3]
+// (five Hessians, three multiplier buffers, the returned multipliers), reduction scratch and
+// the adjoint's own control blocks (the forward solve's stay as its last solve left them)
 static int ensure_adj(dgp_plan* pl) {
   if (pl->adj) return DGP_OK;
   const size_t bn = (size_t)pl->batch * pl->n3;
-  TRY(dalloc(pl, &pl->adj, 15 * bn));
-  TRY(dalloc(pl, &pl->adj_red, (size_t)adjoint_groups(pl->n3) * pl->batch * 2));
+  TRY(dalloc(pl, &pl->adj, 9 * bn));
+  const size_t red = std::max((size_t)adjoint_groups(pl->n3) * 2, (size_t)adj_step_groups(pl->n) * 3);
+  TRY(dalloc(pl, &pl->adj_red, red * pl->batch));
+  TRY(dalloc(pl, &pl->adj_vec, pl->batch));
+  void* d = nullptr;
+  if (hipMalloc(&d, sizeof(SolveCtl) * pl->batch) != hipSuccess) return fail(DGP_E_NOMEM, "adjoint control blocks");
+  pl->dev_allocs.push_back(d);
+  pl->adj_ctl = static_cast<SolveCtl*>(d);
+  void* h = nullptr;
+  if (hipHostMalloc(&h, sizeof(SolveCtl) * pl->batch, hipHostMallocDefault) != hipSuccess)
+    return fail(DGP_E_NOMEM, "adjoint control blocks (host)");
+  pl->host_allocs.push_back(h);
+  pl->adj_ctl_host = static_cast<SolveCtl*>(h);
   return DGP_OK;
 }
 
@@ -1135,17 +1152,16 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   const size_t n3 = pl->n3, fs = (size_t)B * pl->hs, bn = (size_t)B * n3;
   TRY(ensure_adj(pl));
   double* H5 = pl->adj;
-  double* P6 = pl->adj + 5 * bn;
-  double* MU = pl->adj + 11 * bn;
-  double* MU2 = pl->adj + 12 * bn;
-  double* Q = pl->adj + 13 * bn;
-  double* RES = pl->adj + 14 * bn;
+  double* MU = pl->adj + 5 * bn;    // three multiplier buffers, bn apart
+  double* RES = pl->adj + 8 * bn;   // the returned multipliers, gathered per element
   const SpecCoef cf = spec_coef(pl, p);
   const double lam = p->lambda, w = p->w, alpha = p->alpha;
-  const int G = adjoint_groups(n3);
+  const AdjCoef ak{2.0 * lam, w, alpha, 2.0 * (1.0 - w) * lam};
+  const int G = adjoint_groups(n3), GS = adj_step_groups(n);
   // Hessians of u* (h00, h11, h01, h02, h12) and <u*>
   TRY(hessians(pl, p, u_star, H5, s));
-  launch_adj_init(n3, B, grad_u, u_star, MU, 2.0 * (1.0 - w) * lam, alpha, pl->adj_red, s);
+  // mu_0 = g / D into buffer 0, with the checks that D stays away from 0 and g is finite
+  launch_adj_init(n3, B, grad_u, u_star, MU, ak.dscale, alpha, pl->adj_red, s);
   launch_pair_means(pl->adj_red, G, n3, B, pl->vec, pl->vec + B, s);
   LAUNCHCHK();
   std::vector<double> host(2 * B);
@@ -1158,47 +1174,53 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
                   "exist there", b);
     if (host[B + b] > 0.0) return fail(DGP_E_INVALID, "batch element %d: grad_u is not finite", b);
   }
-  std::vector<int> done(B, 0), iters(B, 0);
-  std::vector<double> resid(B, 0.0), rmin(B, 1e300);
-  int it = 0;
-  for (;; ++it) {
-    launch_adj_products(n3, B, MU, u_star, H5, pl->mean_u, P6, pl->adj_red, s);
-    launch_pair_means(pl->adj_red, G, n3, B, pl->vec, nullptr, s);
-    launch_p1_fwd<double>(n, P6, pl->spec6, 6 * B, nullptr, s);
-    launch_p2<double>(n, pl->spec6, 6, B, -1, nullptr, s);
-    launch_p3<double>(n, SPEC_ADJ_COMBINE, pl->spec6, fs, 6, pl->spec_u, fs, 1, B, cf, nullptr, nullptr, nullptr,
-                      nullptr, s);
-    launch_p2<double>(n, pl->spec_u, 1, B, +1, nullptr, s);
-    launch_p1_inv<double>(n, pl->spec_u, Q, B, nullptr, s);
-    launch_adj_update(n3, B, Q, MU, MU2, u_star, H5, pl->mean_u, pl->vec, grad_u, lam, w, alpha, pl->adj_red, s);
-    launch_pair_means(pl->adj_red, G, n3, B, pl->vec + B, pl->vec + 2 * B, s);
-    LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(host.data(), pl->vec + B, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    // RES keeps, per element, the minimum-residual mu seen (returned if max_iter is reached) or
-    // the converged one
-    int active = 0;
-    for (int b = 0; b < B; ++b) {
-      if (done[b]) continue;
-      const double r = host[B + b] > 0.0 ? host[b] / host[B + b] : 0.0;
-      resid[b] = r;
-      const bool conv = r <= p->tol;
-      if (conv || r < rmin[b])
-        HIPCHK(hipMemcpyAsync(RES + (size_t)b * n3, MU + (size_t)b * n3, sizeof(double) * n3,
-                              hipMemcpyDeviceToDevice, s));
-      rmin[b] = std::min(rmin[b], r);
-      if (conv || it >= p->max_iter || r != r) {
-        done[b] = conv ? 1 : 2;
-        iters[b] = it;
-        if (!conv) resid[b] = rmin[b];
-      } else {
-        ++active;
-      }
-    }
-    if (active == 0) break;
-    std::swap(MU, MU2);
+  // device control: element b's multiplier k lives in MU + buf * bn + b * n3 (buffers rotate)
+  for (int b = 0; b < B; ++b) {
+    SolveCtl& C = pl->adj_ctl_host[b];
+    std::memset(&C, 0, sizeof(SolveCtl));
+    C.cur = 0;
+    C.out = 1;
+    C.best = 0;
+    C.resid_min = std::numeric_limits<double>::infinity();
   }
-  // dL/ddelta = S mu (multiplier A (1 - beta/kbar), k = 0 -> 0)
+  HIPCHK(hipMemcpyAsync(pl->adj_ctl, pl->adj_ctl_host, sizeof(SolveCtl) * B, hipMemcpyHostToDevice, s));
+  // products of mu_0 and their axis-0 transforms, <h22 mu_0>
+  launch_adj_step(n, false, nullptr, MU, bn, u_star, H5, grad_u, pl->mean_u, pl->adj_vec, pl->spec6, fs, pl->adj_red,
+                  ak, pl->adj_ctl, B, s);
+  launch_adj_finalize(false, pl->adj_red, GS, pl->adj_ctl, pl->adj_vec, n3, p->tol, p->max_iter, B, s);
+  LAUNCHCHK();
+  // iterations in chunks; the host only reads the control blocks between chunks (iterations of
+  // an element that has decided exit at once)
+  const int limit = std::max(p->max_iter, 0) + 1;   // evaluations an element can take
+  int enqueued = 0;
+  int chunk = 4;
+  while (enqueued < limit) {
+    const int m = std::min(chunk, limit - enqueued);
+    for (int j = 0; j < m; ++j) {
+      launch_p2<double>(n, pl->spec6, 6, B, -1, pl->adj_ctl, s);
+      launch_p3<double>(n, SPEC_ADJ_COMBINE, pl->spec6, fs, 6, pl->spec_u, fs, 1, B, cf, nullptr, nullptr, nullptr,
+                        pl->adj_ctl, s);
+      launch_p2<double>(n, pl->spec_u, 1, B, +1, pl->adj_ctl, s);
+      launch_adj_step(n, true, pl->spec_u, MU, bn, u_star, H5, grad_u, pl->mean_u, pl->adj_vec, pl->spec6, fs,
+                      pl->adj_red, ak, pl->adj_ctl, B, s);
+      launch_adj_finalize(true, pl->adj_red, GS, pl->adj_ctl, pl->adj_vec, n3, p->tol, p->max_iter, B, s);
+    }
+    LAUNCHCHK();
+    enqueued += m;
+    HIPCHK(hipMemcpyAsync(pl->adj_ctl_host, pl->adj_ctl, sizeof(SolveCtl) * B, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool all = true;
+    for (int b = 0; b < B; ++b) all = all && pl->adj_ctl_host[b].done;
+    if (all) break;
+    chunk = std::min(2 * chunk, 16);
+  }
+  // gather each element's returned multipliers, then dL/ddelta = S mu (multiplier A (1 - beta/kbar), k = 0 -> 0)
+  for (int b = 0; b < B; ++b) {
+    const SolveCtl& C = pl->adj_ctl_host[b];
+    if (!C.done) return fail(DGP_E_HIP, "adjoint control block %d undecided after max_iter", b);
+    HIPCHK(hipMemcpyAsync(RES + (size_t)b * n3, MU + (size_t)C.result * bn + (size_t)b * n3, sizeof(double) * n3,
+                          hipMemcpyDeviceToDevice, s));
+  }
   TRY(fwd3<double>(pl, RES, pl->spec_u, B, nullptr, s));
   launch_p3<double>(n, SPEC_SOURCE, pl->spec_u, fs, 1, pl->spec6, fs, 2, B, cf, nullptr, nullptr, nullptr, nullptr, s);
   launch_p2<double>(n, pl->spec6, 1, B, +1, nullptr, s);
@@ -1207,16 +1229,17 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   HIPCHK(hipStreamSynchronize(s));
   int worst = DGP_OK;
   for (int b = 0; b < B; ++b) {
-    const int st = done[b] == 1 ? DGP_OK : DGP_NOT_CONVERGED;
+    const SolveCtl& C = pl->adj_ctl_host[b];
+    const int st = C.status == 0 ? DGP_OK : DGP_NOT_CONVERGED;
     if (st != DGP_OK) worst = st;
     if (info) {
       std::memset(&info[b], 0, sizeof(dgp_info));
       info[b].status = st;
-      info[b].iters = iters[b];
-      info[b].passes = iters[b] + 1;
-      info[b].passes_fp64 = iters[b] + 1;
-      info[b].resid = resid[b];
-      info[b].resid_min = rmin[b];
+      info[b].iters = C.iters;
+      info[b].passes = C.passes;
+      info[b].passes_fp64 = C.passes;
+      info[b].resid = C.resid;
+      info[b].resid_min = C.resid_min;
     }
   }
   return worst;

@@ -196,11 +196,21 @@ int adjoint_groups(size_t n3);
 // in part (adjoint_groups(n3) x batch x 2 doubles)
 void launch_adj_init(size_t n3, int batch, const double* g, const double* u, double* mu, double dscale, double alpha,
                      double* part, hipStream_t s);
-void launch_adj_products(size_t n3, int batch, const double* mu, const double* u, const double* h5,
-                         const double* mean_u, double* p6, double* part, hipStream_t s);
-void launch_adj_update(size_t n3, int batch, const double* q, const double* mu, double* mu_new, const double* u,
-                       const double* h5, const double* mean_u, const double* mean_h22mu, const double* g, double lam,
-                       double w, double alpha, double* part, hipStream_t s);
+// coefficients of the transposed update: 2 lam, w, alpha and D's slope 2 (1-w) lam
+struct AdjCoef {
+  double lam2, w, alpha, dscale;
+};
+// workgroups per batch element of launch_adj_step (its partial sums: [batch][groups][3])
+int adj_step_groups(int n);
+// one fused adjoint iteration step (see adjoint.hip); mubuf holds three multiplier buffers
+// mu_stride apart, indexed by ctl[b].cur / ctl[b].out; spec6: six half spectra spec_stride apart
+void launch_adj_step(int n, bool update, const cx<double>* qspec, double* mubuf, size_t mu_stride, const double* u,
+                     const double* h5, const double* g, const double* mean_u, const double* mean_h22mu,
+                     cx<double>* spec6, size_t spec_stride, double* part, const AdjCoef& k, const SolveCtl* ctl,
+                     int batch, hipStream_t s);
+// <h22 mu'> per element and, with eval, the convergence decision of the step just run
+void launch_adj_finalize(bool eval, const double* part, int groups, SolveCtl* ctl, double* mean_h22mu, size_t n3,
+                         double tol, int max_iter, int batch, hipStream_t s);
 
 // counts of points where Eq. FullDGP2 is not elliptic (Appendix), per workgroup into part
 // (adjoint_groups(n3) x batch x 2 doubles); launch_pair_means turns them into fractions
