@@ -20,6 +20,8 @@ Other modes:
                           particles (box 1024 Mpc/h), precision form and plain float64 form
   --wscan                 the w-scan of Fig. 3 at the paper's size (z = 24, box 64 Mpc/h,
                           256^3 mesh, 128^3 particles): residual and bad fraction per pass
+  --adjoint               the implicit adjoint of 8 batched 128^3 log-normal fields (float64,
+                          backward to 1e-12): time per backward and per iteration
 
 The solve runs in the precision form (float32 FFTs and pointwise storage,
 float64 residual / discriminant / root / reductions, float64 polish); the plain
@@ -280,6 +282,51 @@ def stages_512(args, torch, dgp, inputs, dev):
     print(json.dumps(out))
 
 
+def adjoint_bench(args, torch, dgp, inputs, dev):
+    """One JSON line: the implicit adjoint of the batched differentiation workload (8 seeded
+    log-normal 128^3 fields, sigma 0.3/1/3, box 256 Mpc/h, lambda for a nonlinear ratio of 3),
+    float64: the backward solve to 1e-12 from a converged forward solve, timed over repeats."""
+    n, box, sig = 128, 256.0, [0.3, 0.3, 0.3, 1.0, 1.0, 1.0, 3.0, 3.0]
+    B = len(sig)
+    deltas = np.stack([inputs.lognormal_delta(n, box, s, 500 + i) for i, s in enumerate(sig)])
+    d = torch.from_numpy(deltas).to(dev)
+    prm0 = dgp.params(OM0, A)
+    with dgp.Plan(n, box, batch=B) as plan:
+        ulin = torch.zeros_like(d)
+        plan.solve_field(dgp.params(OM0, A, tol=0.0, max_iter=0), d, ulin)
+        lam = float(np.median([3.0 * prm0.alpha / float(ulin[b].abs().max()) for b in range(B)]))
+        u = torch.zeros_like(d)
+        st, _ = plan.solve_field(dgp.params(OM0, A, lam=lam, tol=1e-12, max_iter=200), d, u)
+        g = torch.from_numpy(np.random.default_rng(77).standard_normal((B, n, n, n))).to(dev)
+        gd = torch.zeros_like(d)
+        bwd = dgp.params(OM0, A, lam=lam, tol=1e-12, max_iter=200)
+        plan.solve_field_backward(bwd, d, u, g, gd)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 10))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, info = plan.solve_field_backward(bwd, d, u, g, gd)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+    iters = [i["iters"] for i in info]
+    evals = [i["passes"] for i in info]
+    hs, n3 = (n // 2 + 1) * n * n, n ** 3
+    # algorithmic bytes of one iteration of one element: axis-1 forward of six spectra (12 hs),
+    # combine (6 in, 1 out), axis-1 inverse (2 hs); the fused axis-0 step reads the combined
+    # spectrum and nine real fields (mu, u, g, five Hessians), writes mu' and six spectra.
+    # Elements stop at their own iteration counts; the setup (Hessians of u*, the first
+    # products) and the final S mu transform are in the time but not in these bytes.
+    it_bytes = (12 + 7 + 2 + 1 + 6) * hs * 16 + (9 + 1) * n3 * 8
+    total = it_bytes * sum(evals)
+    out = {"mode": "adjoint", "config": {"workload": "implicit adjoint of 8 batched 128^3 log-normal fields "
+                                                     "(sigma 0.3/1/3), float64, backward to 1e-12",
+                                         "mesh": n, "batch": B, "lambda": lam},
+           "status": st, "ms_backward": ms, "iters": iters, "evaluations": evals,
+           "bytes_per_element_iteration": it_bytes, "algorithmic_GB": total * 1e-9,
+           "GBps": total / ms * 1e-6, "resid": [i["resid"] for i in info]}
+    print(json.dumps(out))
+
+
 def wscan(args, torch, dgp, inputs, dev):
     """One JSON line: the convergence histories of Fig. 3 (Sec. III C) at the paper's size.  A seeded
     Zel'dovich load of 128^3 particles (P ~ k^-1.5 exp(-k^2/k_c^2), k_c = 4 h/Mpc, rms displacement
@@ -360,6 +407,8 @@ def main():
     ap.add_argument("--stages", action="store_true",
                     help="per-stage times of a 512^3 PM step with 512^3 float32 particles, both forms")
     ap.add_argument("--wscan", action="store_true", help="the w-scan of Fig. 3 at the paper's size")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the implicit adjoint of the batched 8 x 128^3 differentiation workload")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="write a per-kernel duration table from a rocprofv3 kernel trace to stdout")
     args = ap.parse_args()
@@ -384,6 +433,9 @@ def main():
         return
     if args.wscan:
         wscan(args, torch, dgp, inputs, dev)
+        return
+    if args.adjoint:
+        adjoint_bench(args, torch, dgp, inputs, dev)
         return
     print("bench: building inputs", file=sys.stderr, flush=True)
     pos_h, psi_h = inputs.zeldovich_load(N, BOX, SEED, block=BLOCK)
