@@ -37,7 +37,7 @@ namespace dgp {
 #define DGP_PLAN_P2_F32 1
 #endif
 #ifndef DGP_PLAN_P3_F64
-#define DGP_PLAN_P3_F64 0
+#define DGP_PLAN_P3_F64 2
 #endif
 #ifndef DGP_PLAN_P3_F32
 #define DGP_PLAN_P3_F32 2

@@ -44,6 +44,10 @@ const cx<T>* twiddles(int n);
 #ifndef DGP_RELAX_MINW_F32
 #define DGP_RELAX_MINW_F32 1
 #endif
+// column pairs of the float32 kernel from N = 512 on
+#ifndef DGP_RELAX_TP_WIDE_F32
+#define DGP_RELAX_TP_WIDE_F32 16
+#endif
 // smallest N whose float32 relaxation kernel pairs its lanes: the two threads whose transform
 // elements e and N - e share a spectral row sit in one wavefront and load that row in the same
 // instruction (one request instead of two)
@@ -74,7 +78,7 @@ struct RelaxGeo {
   static constexpr bool kWide = N >= 512;
   using P = typename PlanPick<N, (kWide ? 0 : DGP_PLAN_RELAX_F32)>::type;
   static constexpr int R = P::R;
-  using G = RelaxTile<T, N, R, (kWide ? 16 : DGP_RELAX_TP_F32)>;
+  using G = RelaxTile<T, N, R, (kWide ? DGP_RELAX_TP_WIDE_F32 : DGP_RELAX_TP_F32)>;
   // minimum wavefronts per SIMD the register allocation plans for (second launch bound)
   static constexpr int kMinWaves = DGP_RELAX_MINW_F32;
   // accumulators of the float32 form (sum h^2 and -(h00 + h11)): float32 or float64; the
@@ -343,6 +347,10 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 #ifndef DGP_RELAXW_MINW_F64
 #define DGP_RELAXW_MINW_F64 3
 #endif
+// column pairs of the float64 kernel from N = 512 on
+#ifndef DGP_RELAXW_TP_WIDE_F64
+#define DGP_RELAXW_TP_WIDE_F64 8
+#endif
 // smallest N whose float64 relaxation kernel reads its twiddles from LDS
 #ifndef DGP_RELAXW_TWLDS_MIN
 #define DGP_RELAXW_TWLDS_MIN 512
@@ -356,7 +364,7 @@ struct RelaxWGeo {
   using P = typename PlanPick<N, (kWide ? 0 : DGP_PLAN_RELAX)>::type;
   static constexpr int R = P::R;
   using G = AxisTile<T, N, R>;
-  static constexpr int kTPSet = kWide ? 8 : DGP_RELAXW_TP_F64;
+  static constexpr int kTPSet = kWide ? DGP_RELAXW_TP_WIDE_F64 : DGP_RELAXW_TP_F64;
   static constexpr int kTP = kTPSet > 0 ? (kTPSet < N / 2 ? kTPSet : N / 2) : G::kTP;
   static constexpr int kT = G::kT, kThreads = kTP * kT, H = N / 2 + 1;
   static constexpr int kMinWaves = kWide ? 2 : DGP_RELAXW_MINW_F64;   // the LDS tile allows one workgroup per CU from N = 512
