@@ -189,7 +189,9 @@ int dgp_step(dgp_plan* plan, const dgp_params* p, void* pos, void* vel, int is_f
  * D = 2 (1-w) lam u + alpha <= 1e-12 alpha (the vertex value of a bad point, up to rounding: the
  * solve did not converge there and the transposed relaxation would divide by about zero) or
  * non-finite values, or when
- * grad_u is not finite.  Synchronises once per transposed-relaxation iteration. */
+ * grad_u is not finite.  Convergence is decided on the device; the call synchronises the stream
+ * between chunks of 4, 8, then 16 transposed-relaxation iterations and returns when grad_delta
+ * is complete. */
 int dgp_solve_field_backward(dgp_plan* plan, const dgp_params* p, const double* delta, const double* u_star,
                              const double* grad_u, double* grad_delta, dgp_info* info, void* stream);
 
