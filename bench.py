@@ -17,7 +17,8 @@ Other modes:
                           WRITE_SIZE) into the traffic summary kept under profiles/
   --trace-summary T       per-kernel duration table of a rocprofv3 kernel trace
   --stages                per-stage times of a PM step on a 512^3 mesh with 512^3 float32
-                          particles (box 1024 Mpc/h), precision form and plain float64 form
+                          particles (box 1024 Mpc/h), precision form and plain float64 form;
+                          with --cpu also the CPU oracle on that step (sampled, extrapolated)
   --wscan                 the w-scan of Fig. 3 at the paper's size (z = 24, box 64 Mpc/h,
                           256^3 mesh, 128^3 particles): residual and bad fraction per pass
   --adjoint               the implicit adjoint of 8 batched 128^3 log-normal fields (float64,
@@ -225,6 +226,8 @@ def stages_512(args, torch, dgp, inputs, dev):
     prm0 = dgp.params(OM0, A)
     growth = A * A * prm0.E * ((prm0.eta - 1.0) / prm0.eta) ** 0.55
     vel0 = torch.from_numpy((growth * psi_h).astype(np.float32)).to(dev)
+    sub = CPU512_SUB
+    cpu_pos, cpu_vel = (pos_h[:, ::sub].copy(), (growth * psi_h[:, ::sub]).astype(np.float32)) if args.cpu else (None, None)
     del pos_h, psi_h
     with dgp.Plan(n, box) as p64:
         delta = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
@@ -279,7 +282,67 @@ def stages_512(args, torch, dgp, inputs, dev):
             "stage_ms_per_step": {k: v[0] / steps for k, v in tim.items()},
             "stage_launches_per_step": {k: v[1] / steps for k, v in tim.items()},
         }
+    if args.cpu:
+        print("bench: the oracle at 512^3 on the host", file=sys.stderr, flush=True)
+        out["cpu_oracle"] = oracle_512(cpu_pos, cpu_vel, lam, n, box, npart, out["fp64_form"]["passes_per_step"])
     print(json.dumps(out))
+
+
+CPU512_SUB = 8   # the oracle's particle stages at 512^3 run on every 8th particle and are scaled by 8
+
+
+def oracle_512(pos_s, vel_s, lam, n, box, npart, passes):
+    """The CPU oracle on the 512^3 step, timed on the host and extrapolated linearly: the deposit,
+    interpolation and kick-drift on every CPU512_SUB-th particle (times scaled by CPU512_SUB), the
+    solve's set-up plus one residual evaluation and one further pass (update + evaluation) on the
+    subsample's delta (scaled to `passes` passes), and the force mesh; one thread and all cores."""
+    from oracle import field as fld, pm, spectral
+    sub = CPU512_SUB
+    prm = fld.SolveParams.from_cosmology(OM0, A, lam=lam, tol=TOL, max_iter=200)
+
+    def say(msg):
+        print("bench: oracle 512^3 " + msg, file=sys.stderr, flush=True)
+
+    def leg():
+        t = {}
+        t0 = time.perf_counter()
+        _, delta = pm.deposit(pos_s, n, box)
+        t["deposit"] = (time.perf_counter() - t0) * sub
+        say("deposit done")
+        t0 = time.perf_counter()
+        u, _ = fld.solve(delta, box, prm, fixed_iters=0)
+        say("first evaluation done")
+        t_first = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fld.solve(delta, box, prm, fixed_iters=1)
+        t_pass = time.perf_counter() - t0 - t_first
+        t["solve"] = t_first + (passes - 1) * t_pass
+        say("pass done")
+        t0 = time.perf_counter()
+        mesh = pm.force_mesh(pm.phi_spectrum(delta, u, box, prm, OM0, A), box)
+        t["force_mesh"] = time.perf_counter() - t0
+        say("force mesh done")
+        t0 = time.perf_counter()
+        force = pm.cic_interpolate(mesh, pos_s, box)
+        t["interpolation"] = (time.perf_counter() - t0) * sub
+        t0 = time.perf_counter()
+        pm.kick_drift(pos_s, vel_s, force, A, DLNA, OM0, box)
+        t["kick_drift"] = (time.perf_counter() - t0) * sub
+        return t, t_first, t_pass
+
+    cores = os.cpu_count() or 1
+    t1, f1, p1 = leg()
+    with spectral.fft_workers(cores):
+        tn, fn, pn = leg()
+    step1, stepn = sum(t1.values()), sum(tn.values())
+    return {"unit": "cells*iter/s", "cpu_model": cpu_model(), "host_logical_cpus": cores,
+            "sample": "deposit, interpolation and kick-drift on 1/%d of the %d particles (x%d); the solve's "
+                      "set-up + first evaluation and one further pass timed, extrapolated to %g passes; "
+                      "the force mesh once" % (sub, npart, sub, passes),
+            "one_thread": {"value": n ** 3 * passes / step1, "step_seconds": step1, "stage_seconds": t1,
+                           "first_evaluation_seconds": f1, "pass_seconds": p1},
+            "all_cores": {"value": n ** 3 * passes / stepn, "cores": cores, "step_seconds": stepn,
+                          "stage_seconds": tn, "first_evaluation_seconds": fn, "pass_seconds": pn}}
 
 
 def adjoint_bench(args, torch, dgp, inputs, dev):
@@ -406,6 +469,8 @@ def main():
     ap.add_argument("--pmc-mesh", type=int, default=256, help="mesh size the counter passes ran at")
     ap.add_argument("--stages", action="store_true",
                     help="per-stage times of a 512^3 PM step with 512^3 float32 particles, both forms")
+    ap.add_argument("--cpu", action="store_true",
+                    help="with --stages: also time the CPU oracle on the 512^3 step (sampled, extrapolated)")
     ap.add_argument("--wscan", action="store_true", help="the w-scan of Fig. 3 at the paper's size")
     ap.add_argument("--adjoint", action="store_true",
                     help="time the implicit adjoint of the batched 8 x 128^3 differentiation workload")
