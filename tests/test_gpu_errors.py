@@ -154,17 +154,17 @@ def test_adjoint_rejects_vertex_points(dgp):
             plan.solve_field_backward(gpu_params(dgp, lam=lam, tol=1e-12), to_dev(delta), to_dev(u2), to_dev(g), gd)
 
 
-def test_adjoint_max_iter(dgp):
+@pytest.mark.parametrize("k", [0, 1, 3])
+def test_adjoint_max_iter(dgp, k):
     """The transposed relaxation stopped at max_iter returns DGP_NOT_CONVERGED and the
     minimum-residual mu; here the residual decreases monotonically, so that is the oracle's
-    mu after the same number of updates."""
-    say("adjoint max_iter")
+    mu after the same number of updates (k = 0: the first multiplier g / D itself)."""
+    say("adjoint max_iter", k)
     n, box = 16, 32.0
     delta, lam = _c1(n, box, seed=6, rnl=3.0)
     op = oracle_params(lam=lam, tol=1e-13, max_iter=200)
     u, _ = fld.solve(delta, box, op)
     g = np.random.default_rng(4).standard_normal(u.shape)
-    k = 3
     _, gd_ref, hist = adjoint.adjoint_picard(u, g, box, op, tol=0.0, max_iter=k + 1)
     assert all(a > b for a, b in zip(hist, hist[1:]))
     with dgp.Plan(n, box) as plan:
@@ -175,6 +175,42 @@ def test_adjoint_max_iter(dgp):
         assert abs(info[0]["resid"] - hist[k]) <= 1e-10 * hist[k]
         _, gd_k, _ = adjoint.adjoint_picard(u, g, box, op, tol=0.0, max_iter=k)
         assert rel_l2(gd.cpu().numpy().reshape(n, n, n), gd_k) <= 1e-11
+
+
+def test_adjoint_batch_stops_per_element(dgp):
+    """A batch whose elements stop at different iterations: the easy field converges and returns its
+    converged multiplier while the other, still running, stops at max_iter with its own
+    minimum-residual multiplier; each against the oracle's transposed relaxation of that field."""
+    say("adjoint batch stops")
+    n, box = 16, 32.0
+    d_easy = inputs.lognormal_delta(n, box, 0.3, 21)
+    d_hard = inputs.lognormal_delta(n, box, 3.0, 22)
+    lam = calibrate_lambda(d_hard, box, 3.0)
+    op = oracle_params(lam=lam, tol=1e-13, max_iter=200)
+    us = [fld.solve(d, box, op)[0] for d in (d_easy, d_hard)]
+    rng = np.random.default_rng(23)
+    gs = [rng.standard_normal((n, n, n)) for _ in range(2)]
+    with dgp.Plan(n, box, batch=2) as plan:
+        args = (to_dev(np.stack([d_easy, d_hard])), to_dev(np.stack(us)), to_dev(np.stack(gs)))
+        gd = torch.zeros((2, n ** 3), dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field_backward(gpu_params(dgp, lam=lam, tol=1e-12, max_iter=200), *args, gd)
+        assert st == 0
+        i_easy, i_hard = info[0]["iters"], info[1]["iters"]
+        assert i_easy + 2 <= i_hard, (i_easy, i_hard)
+        m = (i_easy + i_hard) // 2
+        st, info = plan.solve_field_backward(gpu_params(dgp, lam=lam, tol=1e-12, max_iter=m), *args, gd)
+        assert st == dgp._lib.DGP_NOT_CONVERGED
+        assert info[0]["status"] == 0 and info[0]["iters"] == i_easy
+        assert info[1]["status"] == dgp._lib.DGP_NOT_CONVERGED and info[1]["iters"] == m
+        got = gd.cpu().numpy().reshape(2, n, n, n)
+        _, ref_easy, _ = adjoint.adjoint_picard(us[0], gs[0], box, op, tol=1e-12, max_iter=200)
+        assert rel_l2(got[0], ref_easy) <= 1e-10
+        _, ref_hard, _ = adjoint.adjoint_picard(us[1], gs[1], box, op, tol=0.0, max_iter=m)
+        _, _, hist = adjoint.adjoint_picard(us[1], gs[1], box, op, tol=0.0, max_iter=m + 1)
+        assert all(a > b for a, b in zip(hist, hist[1:]))   # the minimum-residual multiplier is the last
+        # (the residual is a difference of O(1) terms: its float64 rounding floor is ~1e-16 absolute)
+        assert abs(info[1]["resid"] - hist[m]) <= 1e-10 * hist[m] + 1e-14
+        assert rel_l2(got[1], ref_hard) <= 1e-11
 
 
 def test_autograd_refuses_unconverged_solve(dgp):
