@@ -60,6 +60,11 @@ const cx<T>* twiddles(int n);
 #ifndef DGP_RELAX_REMAT_MIN
 #define DGP_RELAX_REMAT_MIN 512
 #endif
+// smallest N whose float32 relaxation kernel keeps the running h22 = -(h00 + h11) in LDS (each
+// thread its own slots) instead of registers across the field loop
+#ifndef DGP_RELAX_PARK_MIN
+#define DGP_RELAX_PARK_MIN 512
+#endif
 
 // axis-0 tile of the relaxation kernel: AxisTile with an optional number of column pairs
 template <typename T, int N, int R, int TPSET>
@@ -87,6 +92,7 @@ struct RelaxGeo {
   // lane order of the paired loads (needs an even number of transform positions per wavefront)
   static constexpr bool kPaired = N >= DGP_RELAX_PAIRED_MIN && (64 / G::kTP) % 2 == 0;
   static constexpr bool kRemat = N >= DGP_RELAX_REMAT_MIN;
+  static constexpr bool kPark = N >= DGP_RELAX_PARK_MIN;
 };
 
 // sum over the W lanes of a wavefront segment (butterfly order, deterministic)
@@ -195,7 +201,9 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   constexpr bool PAIRED = RG::kPaired;
   int t = !PAIRED ? g : g < 2 ? g * (TT / 2) : (g & 1) ? TT - (g >> 1) : (g >> 1);
   const int i2 = (tile * TP + c) * 2;
-  __shared__ cx<T> lds[N * TP];
+  // transform exchanges, then (kPark) R slots per thread for the running h22
+  __shared__ cx<T> lds[N * TP + (RG::kPark ? R * G::kThreads : 0)];
+  cx<T>* const park = lds + N * TP + threadIdx.x;   // slot q at park[q * kThreads]
   __shared__ double red[(G::kThreads + 63) / 64];
   __shared__ int redi[(G::kThreads + 63) / 64];
   // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
@@ -258,13 +266,22 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
         if (f == 0) {
           s2[q][0] = hx * hx;
           s2[q][1] = hy * hy;
-          h22[q][0] = -hx;
-          h22[q][1] = -hy;
+          if constexpr (RG::kPark) {
+            park[q * G::kThreads] = mk(T(-hx), T(-hy));
+          } else {
+            h22[q][0] = -hx;
+            h22[q][1] = -hy;
+          }
         } else if (f == 1) {
           s2[q][0] += hx * hx;
           s2[q][1] += hy * hy;
-          h22[q][0] -= hx;
-          h22[q][1] -= hy;
+          if constexpr (RG::kPark) {
+            const cx<T> hz = park[q * G::kThreads];
+            park[q * G::kThreads] = mk(hz.x - T(hx), hz.y - T(hy));
+          } else {
+            h22[q][0] -= hx;
+            h22[q][1] -= hy;
+          }
         } else {
           s2[q][0] += Acc(2) * hx * hx;
           s2[q][1] += Acc(2) * hy * hy;
@@ -285,8 +302,17 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     up[q] = *reinterpret_cast<const cx<T>*>(uin + off);
     spv[q] = *reinterpret_cast<const cx<T>*>(sp + off);
   }
+  if constexpr (RG::kPark) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const cx<T> hz = park[q * G::kThreads];
+      h22[q][0] = Acc(hz.x);
+      h22[q][1] = Acc(hz.y);
+    }
+  }
   double un[R][2];
   relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
+  if constexpr (RG::kRemat) asm volatile("" : "+v"(t), "+v"(c));   // the epilogue's addresses from here
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const size_t off = (size_t)(t + q * TT) * N * N;
