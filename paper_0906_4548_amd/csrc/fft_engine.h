@@ -294,25 +294,36 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// LDS accessor for strided columns: element e of column c at base[e * C + c].
-template <typename T, int C>
+// LDS accessor for strided columns: element e of column c at base[e * C + c], with one padding
+// row after every PG rows when PG > 0 (a first radix-r stage stores rows r apart; PG = r
+// spreads them over the banks).  The region holds (N + N / PG) * C elements.
+template <typename T, int C, int PG = 0>
 struct LdsCol {
   cx<T>* base;
   int c;
-  __device__ __forceinline__ cx<T> load(int e) const { return base[e * C + c]; }
-  __device__ __forceinline__ void store(int e, cx<T> v) const { base[e * C + c] = v; }
+  __device__ __forceinline__ int at(int e) const {
+    const unsigned u = unsigned(e);
+    return int(PG > 0 ? u + u / PG : u) * C + c;
+  }
+  __device__ __forceinline__ cx<T> load(int e) const { return base[at(e)]; }
+  __device__ __forceinline__ void store(int e, cx<T> v) const { base[at(e)] = v; }
   __device__ __forceinline__ void sync() const { lds_barrier(); }
 };
 
-// LDS accessor for contiguous rows: element e of row c at base[c * (N + N/16) + e + e/16].
+// padding of the axis-2 pass's LDS rows (measured: 4, 8, 16 and 32 within noise of each other)
+#ifndef DGP_ROW_PAD
+#define DGP_ROW_PAD 16
+#endif
+// LDS accessor for contiguous rows: element e of row c at base[c * (N + N/P) + e + e/P], P = kPad.
 // WAVE: every row is carried by lanes of a single wavefront (N/R <= 64), so the row's LDS
 // exchanges only need ordering within the wavefront, not a workgroup barrier.
 template <typename T, int N, bool WAVE = false>
 struct LdsRow {
   cx<T>* base;
   int c;
-  static constexpr int kStride = N + N / 16;
-  __device__ __forceinline__ int at(int e) const { return c * kStride + e + (e >> 4); }
+  static constexpr int kPad = DGP_ROW_PAD;   // one padding element after every kPad elements
+  static constexpr int kStride = N + N / kPad;
+  __device__ __forceinline__ int at(int e) const { return c * kStride + e + unsigned(e) / kPad; }
   __device__ __forceinline__ cx<T> load(int e) const { return base[at(e)]; }
   __device__ __forceinline__ void store(int e, cx<T> v) const { base[at(e)] = v; }
   __device__ __forceinline__ void sync() const {

@@ -220,7 +220,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
   const bool valid = row < ROWS;
   const int rr = valid ? row : 0;
   const int k0 = rr / N, k1 = rr % N;
-  __shared__ cx<T> lds[RW * (N + N / 16)];
+  __shared__ cx<T> lds[RW * LdsRow<T, N>::kStride];
   // a row's N/R threads are consecutive lanes; when they fit in one wavefront its exchanges are wave-local
   LdsRow<T, N, (TT <= 64 && 64 % TT == 0 && DGP_P3_WAVE_SYNC)> L{lds, c};
   const size_t roff = (size_t)b * ROWS * N + (size_t)rr * N;

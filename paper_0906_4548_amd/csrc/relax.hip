@@ -58,12 +58,16 @@ const cx<T>* twiddles(int n);
 // the per-lane addresses built from them are not held across the field loop (at N = 512 the
 // 1024-thread workgroup leaves 128 VGPRs per lane)
 #ifndef DGP_RELAX_REMAT_MIN
-#define DGP_RELAX_REMAT_MIN 512
+#define DGP_RELAX_REMAT_MIN 256
+#endif
+// padding rows of the float32 kernel's transform exchanges (one after every DGP_RELAX_LDSPAD rows)
+#ifndef DGP_RELAX_LDSPAD
+#define DGP_RELAX_LDSPAD 8
 #endif
 // smallest N whose float32 relaxation kernel keeps the running h22 = -(h00 + h11) in LDS (each
 // thread its own slots) instead of registers across the field loop
 #ifndef DGP_RELAX_PARK_MIN
-#define DGP_RELAX_PARK_MIN 512
+#define DGP_RELAX_PARK_MIN 256
 #endif
 
 // axis-0 tile of the relaxation kernel: AxisTile with an optional number of column pairs
@@ -202,8 +206,9 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   int t = !PAIRED ? g : g < 2 ? g * (TT / 2) : (g & 1) ? TT - (g >> 1) : (g >> 1);
   const int i2 = (tile * TP + c) * 2;
   // transform exchanges, then (kPark) R slots per thread for the running h22
-  __shared__ cx<T> lds[N * TP + (RG::kPark ? R * G::kThreads : 0)];
-  cx<T>* const park = lds + N * TP + threadIdx.x;   // slot q at park[q * kThreads]
+  constexpr int PG = DGP_RELAX_LDSPAD, LROWS = PG > 0 ? N + N / PG : N;
+  __shared__ cx<T> lds[LROWS * TP + (RG::kPark ? R * G::kThreads : 0)];
+  cx<T>* const park = lds + LROWS * TP + threadIdx.x;   // slot q at park[q * kThreads]
   __shared__ double red[(G::kThreads + 63) / 64];
   __shared__ int redi[(G::kThreads + 63) / 64];
   // the twiddle table is read from LDS: the seven transforms of a pass would otherwise wait on
@@ -256,7 +261,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
     }
     if (f < 5) fetch_direct(f + 1);
     {
-      LdsCol<T, TP> L{lds, c};
+      LdsCol<T, TP, PG> L{lds, c};
       fft<T, N, P, +1>(v, twl, L, t);
     }
     if (f < 5) {
@@ -322,7 +327,7 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
   }
   // forward axis-0 transform of u^(n+1)
   {
-    LdsCol<T, TP> L{lds, c};
+    LdsCol<T, TP, PG> L{lds, c};
     fft<T, N, P, -1>(v, twl, L, t);
   }
   lds_barrier();
