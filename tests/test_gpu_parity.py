@@ -437,6 +437,44 @@ def test_run_against_oracle(dgp, prec):
         assert rel_l2(tv.cpu().numpy() - vel, v_ref - vel) <= tol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_run_resumes_from_saved_state(dgp, prec):
+    """A run's state is (positions, velocities, u_state, a): four steps in one call equal two
+    steps, a copy of the state, and two more steps resumed from the copy with a warm start (in a
+    fresh plan, so no plan-held state carries over), up to the rounding of the scale factor (the
+    resumed run forms a = a_2 e^(k dlna) where the whole run forms a_0 e^((k+2) dlna)) and the
+    solve tolerance."""
+    say("run resume", prec)
+    n, box, pos, vel, a0, dlna, lam = _run_case()
+    precision = dgp.FP64 if prec == "fp64" else dgp.FP32
+    prm = dgp.params(OM0, a0, lam=lam, tol=1e-11, max_iter=100)
+    with dgp.Plan(n, box, precision=precision) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, _ = plan.run(prm, tp, tv, u, a0, dlna, 4, 0.47)
+        assert st == 0
+        whole = [x.cpu().numpy() for x in (tp, tv, u)]
+    with dgp.Plan(n, box, precision=precision) as plan:
+        tp, tv = to_dev(pos), to_dev(vel)
+        u = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, _ = plan.run(prm, tp, tv, u, a0, dlna, 2, 0.47)
+        assert st == 0
+        saved = [x.cpu().numpy().copy() for x in (tp, tv, u)]
+    with dgp.Plan(n, box, precision=precision) as plan:
+        tp, tv, u = (to_dev(x) for x in saved)
+        u = u.reshape(-1).contiguous()
+        a2 = a0 * np.exp(2 * dlna)
+        st, _ = plan.run(dgp.params(OM0, a2, lam=lam, tol=1e-11, max_iter=100, init=dgp.INIT_WARM), tp, tv, u, a2,
+                         dlna, 2, 0.47)
+        assert st == 0
+        resumed = [x.cpu().numpy() for x in (tp, tv, u)]
+    dx_w = (whole[0] - pos + box / 2) % box - box / 2
+    dx_r = (resumed[0] - pos + box / 2) % box - box / 2
+    assert rel_l2(dx_r, dx_w) <= 1e-10
+    assert rel_l2(resumed[1] - vel, whole[1] - vel) <= 1e-10
+    assert rel_l2(resumed[2].reshape(-1), whole[2].reshape(-1)) <= 1e-9
+
+
 @pytest.mark.parametrize("mode", [1, 2, 3])
 def test_comparison_runs_against_oracle(dgp, mode):
     """The lDGP, GRH and GR comparison runs (Sec. IV): dgp_run with that force law at every step
