@@ -267,6 +267,26 @@ struct Timed {
   }
 };
 
+// A timed class of one kernel launch: the two events are handed to the launch, which records
+// them as part of its dispatch (no marker packets between this kernel and its neighbours).
+struct TimedLaunch {
+  dgp_plan* pl;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(dgp_plan* p, int c) : pl(p), cls(c) {
+    if (!pl->timing || !((pl->t_mask >> cls) & 1u)) return;
+    a = ev_get(pl);
+    b = a ? ev_get(pl) : nullptr;
+    if (a && !b) {
+      pl->ev_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~TimedLaunch() {
+    if (a && b) pl->pend.push_back({a, b, cls});
+  }
+};
+
 // accumulate completed event pairs (call after the stream has been synchronised)
 static void timing_flush(dgp_plan* pl) {
   for (auto& q : pl->pend) {
@@ -510,8 +530,8 @@ static int enqueue_pass(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const Solve
     launch_p2<T>(n, w.spec6, 6, B, +1, pl->ctl, s);
   }
   {
-    Timed t(pl, s, tcls<T>(DGP_T_RELAX));
-    launch_relax<T>(n, w.spec6, w.U, w.S, w.spec_u, w.partial, pl->mean_u, B, cfg, pl->ctl, s);
+    TimedLaunch t(pl, tcls<T>(DGP_T_RELAX));
+    launch_relax<T>(n, w.spec6, w.U, w.S, w.spec_u, w.partial, pl->mean_u, B, cfg, pl->ctl, s, t.a, t.b);
   }
   {
     Timed t(pl, s, tcls<T>(DGP_T_FINALIZE));

@@ -153,10 +153,12 @@ void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin,
                double* bin_partial, double* mean_out, const SolveCtl* ctl, hipStream_t s);
 int p3_row_groups(int n);   // workgroups per batch element of the axis-2 pass (for POWER partials)
 
-// fused relaxation pass (inverse axis-0 of 6 spectra + pointwise update + forward axis-0)
+// fused relaxation pass (inverse axis-0 of 6 spectra + pointwise update + forward axis-0);
+// ev0/ev1 (may be null): timing events recorded by the kernel's dispatch at its start and end
 template <typename T>
 void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* s_field, cx<T>* spec_u, double* partial,
-                  const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s);
+                  const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s,
+                  hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 int relax_groups(int n, int elem_bytes);   // workgroups per batch element of the fused pass
 
 void launch_finalize(const double* partial, int groups, SolveCtl* ctl, const SolveCfg& cfg,

@@ -21,6 +21,8 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
 #include "dgp_internal.h"
 
 namespace dgp {
@@ -742,36 +744,42 @@ k_absmean_final(const double* __restrict__ part, int groups, size_t n3, double* 
 }
 
 // ------------------------------------------------------------------ launchers
+// (ev0, ev1: optional timing events recorded by the dispatch itself, at the kernel's start and
+// end, without separate marker packets in the stream)
 template <typename T, int N>
 static void relax_n(const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
-                    const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
+                    const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1) {
   constexpr size_t fstride = (size_t)(N / 2 + 1) * N * N;
   if constexpr (sizeof(T) == 8) {
     using W = RelaxWGeo<T, N>;
     dim3 grid(N / (2 * W::kTP), N, batch);
-    hipLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(W::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield,
-                       spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
+    hipExtLaunchKernelGGL((k_relax_w<T, N>), grid, dim3(W::kThreads), 0, s, ev0, ev1, 0, spec6, fstride * batch,
+                          ubuf, sfield, spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
   } else {
     using G = typename RelaxGeo<T, N>::G;
     dim3 grid(N / (2 * G::kTP), N, batch);
-    hipLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, spec6, fstride * batch, ubuf, sfield, spec_u,
-                       partial, mean_u, cfg, ctl, twiddles<T>(N));
+    hipExtLaunchKernelGGL((k_relax<T, N>), grid, dim3(G::kThreads), 0, s, ev0, ev1, 0, spec6, fstride * batch,
+                          ubuf, sfield, spec_u, partial, mean_u, cfg, ctl, twiddles<T>(N));
   }
 }
 
 template <typename T>
 void launch_relax(int n, const cx<T>* spec6, T* ubuf, const T* sfield, cx<T>* spec_u, double* partial,
-                       const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s) {
+                  const double* mean_u, int batch, const SolveCfg& cfg, const SolveCtl* ctl, hipStream_t s,
+                  hipEvent_t ev0, hipEvent_t ev1) {
+#define C(NN) relax_n<T, NN>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s, ev0, ev1)
   switch (n) {
-    case 8: relax_n<T, 8>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 16: relax_n<T, 16>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 32: relax_n<T, 32>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 64: relax_n<T, 64>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 128: relax_n<T, 128>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 256: relax_n<T, 256>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
-    case 512: relax_n<T, 512>(spec6, ubuf, sfield, spec_u, partial, mean_u, batch, cfg, ctl, s); break;
+    case 8: C(8); break;
+    case 16: C(16); break;
+    case 32: C(32); break;
+    case 64: C(64); break;
+    case 128: C(128); break;
+    case 256: C(256); break;
+    case 512: C(512); break;
     default: break;
   }
+#undef C
 }
 
 // column pairs per workgroup of the relaxation kernel that launches for (T, N)
@@ -1010,9 +1018,11 @@ void launch_pair_means(const double* part, int groups, size_t n3, int batch, dou
 }
 
 template void launch_relax<double>(int, const cx<double>*, double*, const double*, cx<double>*, double*,
-                                   const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t);
+                                   const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t, hipEvent_t,
+                                   hipEvent_t);
 template void launch_relax<float>(int, const cx<float>*, float*, const float*, cx<float>*, double*,
-                                  const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t);
+                                  const double*, int, const SolveCfg&, const SolveCtl*, hipStream_t, hipEvent_t,
+                                  hipEvent_t);
 template void launch_absmean<double>(size_t, const double*, int, double*, double*, double*, hipStream_t);
 template void launch_absmean<float>(size_t, const float*, int, double*, double*, double*, hipStream_t);
 
