@@ -419,6 +419,25 @@ def test_bad_points_w0_stop_at_minimum():
     assert i3.status == fld.STATUS_OK and i3.resid <= 1e-12
 
 
+def test_zeldovich_load_nonlinear_ratio_3_meets_bad_points():
+    """The reason the particle-load configurations use r_nl = 1.78: on a 64^3 Zel'dovich load
+    (one particle per cell, rms displacement one cell; voids to delta ~ -0.97) lam fixed by
+    r_nl = 3 drives the deepest voids past the vertex of the local quadratic: the relaxation
+    (w = 1/3, as in the paper) meets bad points and stops at its minimum residual far above the
+    tolerance, while r_nl = 1.78 converges to 1e-10 without any."""
+    n, box = 64, 128.0
+    pos, _ = inputs.zeldovich_load(n, box, 3)
+    _, delta = pm.deposit(pos, n, box)
+    prm0 = fld.SolveParams.from_cosmology(OM0, 0.5, tol=1e-10, max_iter=100)
+    _, sk, _ = fld.source(delta, box, prm0)
+    umax = np.max(np.abs(fld.linear_solution(sk, box, prm0)))
+    _, ok = fld.solve(delta, box, prm0.with_(lam=1.78 * prm0.alpha / umax))
+    assert ok.status == fld.STATUS_OK and ok.resid <= 1e-10 and max(ok.bad_history) == 0
+    _, bad = fld.solve(delta, box, prm0.with_(lam=3.0 * prm0.alpha / umax))
+    assert bad.status == fld.STATUS_BAD_POINTS and max(bad.bad_history) > 1e-3
+    assert bad.resid == min(bad.history) and bad.resid > 1e-4
+
+
 # ---------------------------------------------------------------- PM pieces
 
 def test_deposit_bruteforce_and_uniform_lattice():
