@@ -208,8 +208,8 @@ def algorithmic_bytes(cls, n, elem):
     c = 2 * elem
     return {
         "axis1_fwd": 2 * hs * c,                 # read + write one half spectrum
-        "fanout": 7 * hs * c,                    # read 1, write 6 spectra
-        "axis1_inv": 12 * hs * c,                # 6 spectra read + write
+        "fanout": 4 * hs * c,                    # read 1, write 3 spectra (1/|n|^2 and axis-2 factors)
+        "axis1_inv": 9 * hs * c,                 # read 3, write 6 spectra (axis-1 and axis-0 factors)
         "relax": 7 * hs * c + 3 * n3 * elem,     # read 6 spectra, u, S; write u, 1 spectrum
     }.get(cls)
 

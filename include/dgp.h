@@ -245,8 +245,8 @@ int dgp_fft_inverse(dgp_plan* plan, const double* spectrum, double* field, void*
  * added are the float32 launches of the precision form. */
 enum {
   DGP_T_AXIS1_FWD = 0,   /* forward axis-1 pass of the iterate's spectrum, per relaxation pass */
-  DGP_T_FANOUT = 1,      /* axis-2 pass: forward FFT, 6 spectral multipliers, 6 inverse FFTs */
-  DGP_T_AXIS1_INV = 2,   /* inverse axis-1 pass of the 6 spectra */
+  DGP_T_FANOUT = 1,      /* axis-2 pass: forward FFT, 3 spectral multipliers, 3 inverse FFTs */
+  DGP_T_AXIS1_INV = 2,   /* inverse axis-1 pass: 3 spectra in, 6 out (axis-1 factors) */
   DGP_T_RELAX = 3,       /* fused axis-0 inverse of 6 spectra + pointwise update + axis-0 forward */
   DGP_T_FINALIZE = 4,    /* residual reduction and stopping rules */
   DGP_T_SETUP = 5,       /* source S, eps and linear guess from delta */

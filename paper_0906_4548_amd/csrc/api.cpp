@@ -523,11 +523,11 @@ static int enqueue_pass(dgp_plan* pl, const dgp_params* p, Ws<T>& w, const Solve
   }
   {
     Timed t(pl, s, tcls<T>(DGP_T_FANOUT));
-    launch_p3<T>(n, SPEC_FANOUT6, w.spec_u, fs, 1, w.spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, pl->ctl, s);
+    launch_p3<T>(n, SPEC_HSPLIT, w.spec_u, fs, 1, w.spec6, fs, 3, B, cf, nullptr, nullptr, pl->mean_u, pl->ctl, s);
   }
   {
     Timed t(pl, s, tcls<T>(DGP_T_AXIS1_INV));
-    launch_p2<T>(n, w.spec6, 6, B, +1, pl->ctl, s);
+    launch_p2_split<T>(n, w.spec6, fs, B, pl->ctl, s);
   }
   {
     TimedLaunch t(pl, tcls<T>(DGP_T_RELAX));

@@ -21,6 +21,9 @@ enum SpecMode : int {
   SPEC_COPY = 7,      // identity (plain forward+inverse round trip, for tests)
   SPEC_FWD_ONLY = 8,  // forward axis-2 transform only (spectrum export)
   SPEC_INV_ONLY = 9,  // inverse axis-2 transform only, times 1/N^3 (spectrum import)
+  SPEC_HSPLIT = 10,   // u(k) -> C' = u/|n|^2, i n2 C' and -u/kbar into slots 0, 3 and 5 of the six
+                      // relaxation fields; the axis-1 pass (launch_p2_split) applies the axis-1
+                      // and axis-0 factors of the Hessian multipliers
 };
 
 enum ForceMode : int { FORCE_NLDGP = 0, FORCE_LDGP = 1, FORCE_GRH = 2, FORCE_GR = 3 };
@@ -146,6 +149,12 @@ void launch_p1_inv(int n, const cx<T>* in, T* out, int batch, const SolveCtl* ct
 // nf fields, each [batch][H][N][N]; DIR -1 forward, +1 inverse
 template <typename T>
 void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, hipStream_t s);
+// axis-1 inverse pass of the split Hessian: slots 0, 3, 5 of the six fields (fstride apart, each
+// [batch][H][N][N]) -> all six, with the axis-1 and axis-0 factors (slot 0 -> 0: n0^2, 1: n1^2,
+// 2: n0 n1; slot 3 -> 3: -i n0, 4: -i n1; slot 5 -> 5: 1; a factor odd in n_d is 0 at the Nyquist
+// index of d)
+template <typename T>
+void launch_p2_split(int n, cx<T>* data, size_t fstride, int batch, const SolveCtl* ctl, hipStream_t s);
 // axis-2 pass: nin input arrays (each [batch][H][N][N]) -> nout output arrays
 template <typename T>
 void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out,

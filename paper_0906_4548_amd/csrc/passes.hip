@@ -184,6 +184,87 @@ k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const So
   for (int q = 0; q < R; ++q) base[(size_t)(t + q * TT) * N] = v[q];
 }
 
+// Axis-1 inverse pass of the split Hessian.  The axis-2 pass wrote C' = u/|n|^2 to slot 0, i n2 C'
+// to slot 3 and the nonlocal term to slot 5; k0 is fixed per workgroup here, so this pass applies
+// both remaining factors (axis 1 and axis 0) of each Hessian multiplier n_i n_j / |n|^2:
+//   slot 0 -> 0 (h00: n0^2), 1 (h11: n1^2), 2 (h01: n0 n1);
+//   slot 3 -> 3 (h02: -i n0), 4 (h12: -i n1);  slot 5 -> 5 (1);
+// a factor odd in n_d is 0 at the Nyquist index of d.
+// Plans of the split pass: the input tile is held in registers across the outputs, so the float64
+// pass takes radix 8 (fewer registers per thread than the axis-1 pass's radix 16; measured at
+// 256^3 on gfx950: 229 vs 246 us per launch, float32 keeps radix 16: 116 vs 129 us)
+#ifndef DGP_PLAN_P2S_F64
+#define DGP_PLAN_P2S_F64 0
+#endif
+#ifndef DGP_PLAN_P2S_F32
+#define DGP_PLAN_P2S_F32 DGP_PLAN_P2_F32
+#endif
+template <typename T, int N>
+struct P2SGeo {
+  using P = typename PlanPick<N, sizeof(T) == 4 ? DGP_PLAN_P2S_F32 : DGP_PLAN_P2S_F64>::type;
+  using G = ColTile<T, N, P::R>;
+};
+
+// factor of output o (0..2 - role) of input slot role (0, 1, 2) at axis-1 index k1
+template <typename T, int N>
+__device__ __forceinline__ cx<T> p2s_factor(int role, int o, T n0, bool q0, int k1, cx<T> x) {
+  const T n1 = T(k1 < N / 2 ? k1 : k1 - N);
+  const bool q1 = k1 == N / 2;
+  if (role == 0) {   // real factors
+    const T m = o == 0 ? n0 * n0 : o == 1 ? n1 * n1 : (q0 || q1) ? T(0) : n0 * n1;
+    return scale(x, m);
+  } else if (role == 1) {   // -i n0, -i n1
+    const T m = o == 0 ? (q0 ? T(0) : n0) : (q1 ? T(0) : n1);
+    return mk(m * x.y, -m * x.x);
+  }
+  return x;
+}
+
+// A workgroup takes one column tile of one input slot, holds it in registers and writes every
+// output that derives from it (blockIdx.z = role * batch + element, so the three-output tiles are
+// dispatched first); the tile is read whole before the first store, so output slot + 0 can
+// overwrite it (no other workgroup touches its columns).  The twiddle pointer and the lane index are made opaque per output, so that twiddles, row addresses
+// and factors are not held across the output loop.  (Re-reading the tile from cache for each output
+// instead of holding it measured 470 vs 229 us per float64 launch at 256^3.)
+template <typename T, int N>
+__global__ void __launch_bounds__((P2SGeo<T, N>::G::kThreads))
+k_p2_split(cx<T>* __restrict__ data, size_t fstride, int batch, const cx<T>* __restrict__ tw,
+           const SolveCtl* __restrict__ ctl) {
+  using P = typename P2SGeo<T, N>::P;
+  constexpr int R = P::R;
+  using G = typename P2SGeo<T, N>::G;
+  constexpr int TY = G::kTY, TT = G::kT, H = N / 2 + 1;
+  const int role = blockIdx.z / batch, b = blockIdx.z % batch;
+  if (batch_done(ctl, b)) return;
+  const int k0 = blockIdx.y;
+  const int c = threadIdx.x % TY;
+  int t = threadIdx.x / TY;
+  __shared__ cx<T> lds[N * TY];
+  const int slot = role == 0 ? 0 : role == 1 ? 3 : 5;
+  const size_t off = ((size_t)b * H + k0) * N * N + blockIdx.x * TY + c;
+  const cx<T>* src = data + slot * fstride + off;
+  const T n0 = T(k0);
+  const bool q0 = k0 == N / 2;
+  LdsCol<T, TY> L{lds, c};
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = src[(size_t)(t + q * TT) * N];
+#pragma unroll 1
+  for (int o = 2 - role; o >= 0; --o) {
+    const cx<T>* twq = tw;
+    asm volatile("" : "+s"(twq), "+v"(t));
+    cx<T> w[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      w[q] = p2s_factor<T, N>(role, o, n0, q0, t + q * TT, v[q]);
+    }
+    fft<T, N, P, +1>(w, twq, L, t);
+    cx<T>* dst = data + (slot + o) * fstride + off;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[(size_t)(t + q * TT) * N] = w[q];
+  }
+}
+
 // ------------------------------------------------------------------ axis 2 with spectral multipliers
 struct Mode3 {
   int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
@@ -342,48 +423,50 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
         for (int q = 0; q < R; ++q) { v2[q] = v[q]; v[q] = keep[q]; }
       }
     }
-    if constexpr (MODE == SPEC_FANOUT6) {
+    if constexpr (MODE == SPEC_FANOUT6 || MODE == SPEC_HSPLIT) {
       if (valid && k0 == 0 && k1 == 0 && t == 0 && mean_out != nullptr) mean_out[b] = double(v[0].x) * cf.inv_n3;
     }
-    if constexpr (MODE == SPEC_FANOUT6 && sizeof(T) == 4) {
-      // float32 fields: the six multipliers in float32 (reciprocal and reciprocal-sqrt estimates,
-      // the reciprocal refined by one Newton step), formed once per mode
-      const float ikbs = float(cf.inv_n3 / (cf.kappa * kf));
-      const float in3 = float(cf.inv_n3);
-      float a0[R], a1[R], a2[R], ik2[R], ikb[R];
-      bool z01[R], z02[R], z12[R];
+    if constexpr (MODE == SPEC_HSPLIT) {
+      // The Hessian multipliers n_i n_j / |n|^2 factor as (1/|n|^2) times one factor per axis:
+      // this pass applies 1/|n|^2 and the axis-2 factor i n2 (0 at the Nyquist index), the axis-1
+      // pass (k_p2_split) the axis-1 and axis-0 factors.  Per mode: ic = 1/(N^3 |n|^2) and
+      // ib = -1/(N^3 kappa kf |n|), both 0 at n = 0; float32 fields form them in float32
+      // (reciprocal and reciprocal-sqrt estimates, the reciprocal refined by one Newton step).
+      T ic[R], ib[R], a2[R];
+      const float in3f = float(cf.inv_n3), ikbs = float(cf.inv_n3 / (cf.kappa * kf));
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         const Mode3 m = mode_of(N, k0, k1, t + q * TT);
-        const float ms = float(m.msq);
-        float r = __builtin_amdgcn_rcpf(ms);
-        r = r * (2.0f - ms * r);
         const bool nz = m.msq != 0;
-        ik2[q] = nz ? r * in3 : 0.0f;
-        ikb[q] = nz ? __builtin_amdgcn_rsqf(ms) * ikbs : 0.0f;
-        a0[q] = float(m.n0);
-        a1[q] = float(m.n1);
-        a2[q] = float(m.n2);
-        z01[q] = m.q0 || m.q1;
-        z02[q] = m.q0 || m.q2;
-        z12[q] = m.q1 || m.q2;
+        if constexpr (sizeof(T) == 4) {
+          const float ms = float(m.msq);
+          float r = __builtin_amdgcn_rcpf(ms);
+          r = r * (2.0f - ms * r);
+          ic[q] = nz ? r * in3f : 0.0f;
+          ib[q] = nz ? -__builtin_amdgcn_rsqf(ms) * ikbs : 0.0f;
+        } else {
+          const double ms = double(m.msq);
+          ic[q] = nz ? cf.inv_n3 / ms : 0.0;
+          ib[q] = nz ? -cf.inv_n3 / (cf.kappa * kf * sqrt(ms)) : 0.0;
+        }
+        a2[q] = m.q2 ? T(0) : T(m.n2);
       }
 #pragma unroll 1
-      for (int o = 0; o < 6; ++o) {
+      for (int o = 0; o < 3; ++o) {
         cx<T> w[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          float mult;
-          if (o == 0) mult = a0[q] * a0[q] * ik2[q];
-          else if (o == 1) mult = a1[q] * a1[q] * ik2[q];
-          else if (o == 2) mult = z01[q] ? 0.0f : a0[q] * a1[q] * ik2[q];
-          else if (o == 3) mult = z02[q] ? 0.0f : a0[q] * a2[q] * ik2[q];
-          else if (o == 4) mult = z12[q] ? 0.0f : a1[q] * a2[q] * ik2[q];
-          else mult = -ikb[q];
-          w[q] = scale(v[q], T(mult));
+          if (o == 0) {
+            w[q] = scale(v[q], ic[q]);
+          } else if (o == 1) {   // i n2 C'
+            const T mq = a2[q] * ic[q];
+            w[q] = mk(-mq * v[q].y, mq * v[q].x);
+          } else {
+            w[q] = scale(v[q], ib[q]);
+          }
         }
         fft<T, N, P, +1>(w, tw, L, t);
-        store_row(out + o * out_stride, w);
+        store_row(out + (o == 0 ? 0 : o == 1 ? 3 : 5) * out_stride, w);
       }
       return;
     }
@@ -495,6 +578,12 @@ static void p2_n(cx<T>* data, int nf, int batch, int dir, const SolveCtl* ctl, c
   else hipLaunchKernelGGL((k_p2<T, N, +1>), grid, dim3(G::kThreads), 0, s, data, batch, tw, ctl);
 }
 template <typename T, int N>
+static void p2_split_n(cx<T>* data, size_t fstride, int batch, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
+  using G = typename P2SGeo<T, N>::G;
+  dim3 grid(N / G::kTY, N / 2 + 1, 3 * batch);
+  hipLaunchKernelGGL((k_p2_split<T, N>), grid, dim3(G::kThreads), 0, s, data, fstride, batch, tw, ctl);
+}
+template <typename T, int N>
 static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t os, int batch, const SpecCoef& cf,
                  const double* bc, double* bp, double* mean, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
   using G = RowTile<N, Geo<T, N>::P3::R>;
@@ -513,6 +602,7 @@ static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t o
     case SPEC_COPY: DGP_P3(SPEC_COPY); break;
     case SPEC_FWD_ONLY: DGP_P3(SPEC_FWD_ONLY); break;
     case SPEC_INV_ONLY: DGP_P3(SPEC_INV_ONLY); break;
+    case SPEC_HSPLIT: DGP_P3(SPEC_HSPLIT); break;
   }
 #undef DGP_P3
 }
@@ -560,6 +650,13 @@ void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* c
 #undef C
 }
 template <typename T>
+void launch_p2_split(int n, cx<T>* data, size_t fstride, int batch, const SolveCtl* ctl, hipStream_t s) {
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p2_split_n<T, NN>(data, fstride, batch, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+template <typename T>
 void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out, size_t out_stride,
                int nout, int batch, const SpecCoef& coef, const double* bin_coef, double* bin_partial,
                double* mean_out, const SolveCtl* ctl, hipStream_t s) {
@@ -589,6 +686,8 @@ template void launch_p1_inv<double>(int, const cx<double>*, double*, int, const 
 template void launch_p1_inv<float>(int, const cx<float>*, float*, int, const SolveCtl*, hipStream_t, float*);
 template void launch_p2<double>(int, cx<double>*, int, int, int, const SolveCtl*, hipStream_t);
 template void launch_p2<float>(int, cx<float>*, int, int, int, const SolveCtl*, hipStream_t);
+template void launch_p2_split<double>(int, cx<double>*, size_t, int, const SolveCtl*, hipStream_t);
+template void launch_p2_split<float>(int, cx<float>*, size_t, int, const SolveCtl*, hipStream_t);
 template void launch_p3<double>(int, SpecMode, const cx<double>*, size_t, int, cx<double>*, size_t, int, int,
                                 const SpecCoef&, const double*, double*, double*, const SolveCtl*, hipStream_t);
 template void launch_p3<float>(int, SpecMode, const cx<float>*, size_t, int, cx<float>*, size_t, int, int,

@@ -33,7 +33,9 @@ def test_algorithmic_bytes_of_the_roofline_kernel():
     # field and source read and the field written (float)
     hs = 129 * 256 * 256
     assert bench.algorithmic_bytes("relax", 256, 4) == 7 * hs * 8 + 3 * 256 ** 3 * 4 == 674758656
-    assert bench.algorithmic_bytes("axis1_inv", 256, 8) == 12 * hs * 16
+    # split Hessian: the axis-1 inverse pass reads three spectra and writes six
+    assert bench.algorithmic_bytes("axis1_inv", 256, 8) == 9 * hs * 16
+    assert bench.algorithmic_bytes("fanout", 256, 4) == 4 * hs * 8
 
 
 def _counter_csv(path, rows):
