@@ -199,6 +199,26 @@ k_p2(cx<T>* __restrict__ data, int batch, const cx<T>* __restrict__ tw, const So
 #ifndef DGP_PLAN_P2S_F32
 #define DGP_PLAN_P2S_F32 DGP_PLAN_P2_F32
 #endif
+// Cache policy of the split Hessian passes (1: nontemporal), per element type, from measured
+// pass times at 256^3 and 512^3 on gfx950.  Float32: the axis-2 pass's three outputs (203 MB at
+// 256^3) are stored through the 256 MB last-level cache, where the axis-1 split pass, which reads
+// each of them once (streaming), finds part of them; float64 (405 MB) streams both ways.  The
+// split pass streams its six outputs, which only the relaxation kernel reads.
+#ifndef DGP_HSPLIT_STREAM_STORE_F32
+#define DGP_HSPLIT_STREAM_STORE_F32 0
+#endif
+#ifndef DGP_HSPLIT_STREAM_STORE_F64
+#define DGP_HSPLIT_STREAM_STORE_F64 1
+#endif
+#ifndef DGP_P2S_STREAM_LOAD_F32
+#define DGP_P2S_STREAM_LOAD_F32 1
+#endif
+#ifndef DGP_P2S_STREAM_LOAD_F64
+#define DGP_P2S_STREAM_LOAD_F64 0
+#endif
+#ifndef DGP_P2S_STREAM_STORE
+#define DGP_P2S_STREAM_STORE 1
+#endif
 template <typename T, int N>
 struct P2SGeo {
   using P = typename PlanPick<N, sizeof(T) == 4 ? DGP_PLAN_P2S_F32 : DGP_PLAN_P2S_F64>::type;
@@ -248,7 +268,11 @@ k_p2_split(cx<T>* __restrict__ data, size_t fstride, int batch, const cx<T>* __r
   LdsCol<T, TY> L{lds, c};
   cx<T> v[R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) v[q] = src[(size_t)(t + q * TT) * N];
+  for (int q = 0; q < R; ++q) {
+    if constexpr (sizeof(T) == 4 ? DGP_P2S_STREAM_LOAD_F32 : DGP_P2S_STREAM_LOAD_F64)
+      v[q] = load_stream(&src[(size_t)(t + q * TT) * N]);
+    else v[q] = src[(size_t)(t + q * TT) * N];
+  }
 #pragma unroll 1
   for (int o = 2 - role; o >= 0; --o) {
     const cx<T>* twq = tw;
@@ -261,7 +285,10 @@ k_p2_split(cx<T>* __restrict__ data, size_t fstride, int batch, const cx<T>* __r
     fft<T, N, P, +1>(w, twq, L, t);
     cx<T>* dst = data + (slot + o) * fstride + off;
 #pragma unroll
-    for (int q = 0; q < R; ++q) dst[(size_t)(t + q * TT) * N] = w[q];
+    for (int q = 0; q < R; ++q) {
+      if constexpr (DGP_P2S_STREAM_STORE) store_stream(&dst[(size_t)(t + q * TT) * N], w[q]);
+      else dst[(size_t)(t + q * TT) * N] = w[q];
+    }
   }
 }
 
@@ -466,7 +493,13 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
           }
         }
         fft<T, N, P, +1>(w, tw, L, t);
-        store_row(out + (o == 0 ? 0 : o == 1 ? 3 : 5) * out_stride, w);
+        cx<T>* dsto = out + (o == 0 ? 0 : o == 1 ? 3 : 5) * out_stride;
+        if constexpr (sizeof(T) == 4 ? DGP_HSPLIT_STREAM_STORE_F32 : DGP_HSPLIT_STREAM_STORE_F64) {
+          store_row(dsto, w);
+        } else if (valid) {
+#pragma unroll
+          for (int q = 0; q < R; ++q) dsto[roff + t + q * TT] = w[q];
+        }
       }
       return;
     }
