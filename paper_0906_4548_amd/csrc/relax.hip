@@ -373,7 +373,9 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 // and the workgroup barriers drop from one pair per stage to one per field.  Global
 // traffic stays coalesced: spectral tiles are fetched row-wise into a double-buffered,
 // padded LDS tile; a transform reads its own two columns of the tile and reuses the
-// same slots (only its wavefront touches them) for the exchanges.
+// same slots (only its wavefront touches them) for the exchanges.  Below N = 512, u and S are
+// read row-wise too and redistributed to the transforms through the two tiles once the field
+// loop is done.
 #ifndef DGP_RELAXW_TP_F64
 #define DGP_RELAXW_TP_F64 0
 #endif
@@ -387,6 +389,13 @@ k_relax(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf, c
 // smallest N whose float64 relaxation kernel reads its twiddles from LDS
 #ifndef DGP_RELAXW_TWLDS_MIN
 #define DGP_RELAXW_TWLDS_MIN 512
+#endif
+
+// float64 kernel: u and S read row-wise (consecutive lanes on one row) and redistributed through
+// LDS (1), instead of each lane reading its own transform's elements, 64 rows per instruction (0)
+// (256^3 on gfx950: 345 vs 363 us per launch)
+#ifndef DGP_RELAXW_US_LDS
+#define DGP_RELAXW_US_LDS 1
 #endif
 
 template <typename T, int N>
@@ -405,6 +414,9 @@ struct RelaxWGeo {
   // inverse transforms would need 56 VGPRs across the field loop at N = 512, where the kernel
   // already uses all 256 of a two-waves-per-SIMD allocation
   static constexpr bool kTwLds = N >= DGP_RELAXW_TWLDS_MIN;
+  // u and S read row-wise and redistributed through LDS (below N = 512: the staging registers
+  // would not fit the wide geometry's allocation)
+  static constexpr bool kUsLds = DGP_RELAXW_US_LDS && !kWide;
   static_assert(kT <= 64 && 64 % kT == 0, "a transform must stay inside one wavefront");
   static constexpr int kSP = 2 * kTP + 1;                            // padded tile row, complex
   static constexpr int kTile = H * kSP;
@@ -529,17 +541,54 @@ k_relax_w(const cx<T>* __restrict__ spec6, size_t fstride, T* __restrict__ ubuf,
   // pointwise residual and update (v holds Nf); u^(n+1) is staged in tile 0 (free since the last barrier).
   // The field addresses are formed here, after the field loop, so that they are not held in
   // registers across it.
-  const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
-  const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
   const PointCoef pc = point_coef(cfg, mean_u[b]);
   T* ust = reinterpret_cast<T*>(lds);
   double abs_r = 0.0;
   int nbad = 0;
+  if constexpr (W::kUsLds) {
+    // row-wise reads (TP lanes per row, one column pair each) into tile 0 (u) and tile 1 (S),
+    // rows 2 TP + 1 values apart; tile 1 is free once every wavefront has finished its last
+    // inverse transform (first barrier); the second barrier orders the reads before the forward
+    // transform's exchanges in tile 1
+    constexpr int NU = (N * TP + NT - 1) / NT;
+    const T* ur = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2;
+    const T* sr = sfield + (size_t)b * N3 + (size_t)i1 * N + i2;
+    cx<T> lu[NU], ls[NU];
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int e = t + q * TT;
-    up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
-    spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
+    for (int r = 0; r < NU; ++r) {
+      const int idx = min(int(threadIdx.x) + r * NT, N * TP - 1);
+      const int e = idx / TP, p = idx % TP;
+      lu[r] = *reinterpret_cast<const cx<T>*>(ur + (size_t)e * NN + 2 * p);
+      ls[r] = *reinterpret_cast<const cx<T>*>(sr + (size_t)e * NN + 2 * p);
+    }
+    T* sst = reinterpret_cast<T*>(lds + W::kTile);
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < NU; ++r) {
+      const int idx = min(int(threadIdx.x) + r * NT, N * TP - 1);
+      const int e = idx / TP, p = idx % TP;
+      ust[e * (2 * TP + 1) + 2 * p] = lu[r].x;
+      ust[e * (2 * TP + 1) + 2 * p + 1] = lu[r].y;
+      sst[e * (2 * TP + 1) + 2 * p] = ls[r].x;
+      sst[e * (2 * TP + 1) + 2 * p + 1] = ls[r].y;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
+      up[q] = mk(ust[e * (2 * TP + 1) + 2 * c], ust[e * (2 * TP + 1) + 2 * c + 1]);
+      spv[q] = mk(sst[e * (2 * TP + 1) + 2 * c], sst[e * (2 * TP + 1) + 2 * c + 1]);
+    }
+    lds_barrier();
+  } else {
+    const T* uin = ubuf + ((size_t)cur * cfg.batch + b) * N3 + (size_t)i1 * N + i2 + 2 * c;
+    const T* sp = sfield + (size_t)b * N3 + (size_t)i1 * N + i2 + 2 * c;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int e = t + q * TT;
+      up[q] = *reinterpret_cast<const cx<T>*>(uin + (size_t)e * NN);
+      spv[q] = *reinterpret_cast<const cx<T>*>(sp + (size_t)e * NN);
+    }
   }
   double un[R][2];
   relax_points(pc, up, spv, v, s2, h22, un, abs_r, nbad);
