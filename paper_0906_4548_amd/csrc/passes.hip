@@ -36,11 +36,14 @@ namespace dgp {
 #ifndef DGP_PLAN_P2_F32
 #define DGP_PLAN_P2_F32 1
 #endif
+// Axis 2: radix 8 in both precisions, two LDS exchanges per transform instead of radix 4's three
+// (the split Hessian pass, four transforms per row, is bound by them: 256^3 float32 66 -> 53 us,
+// float64 95 -> 90 us); a row's transform stays inside one wavefront up to N = 512
 #ifndef DGP_PLAN_P3_F64
-#define DGP_PLAN_P3_F64 2
+#define DGP_PLAN_P3_F64 0
 #endif
 #ifndef DGP_PLAN_P3_F32
-#define DGP_PLAN_P3_F32 2
+#define DGP_PLAN_P3_F32 0
 #endif
 // Column tile of the axis-0 passes: AxisTile, widened from N = 512 on, where the planes are
 // 2 MB (float32) or 4 MB (float64) apart and 128-byte row segments per plane stream poorly.
@@ -56,8 +59,7 @@ struct Geo {
   static constexpr bool kF32 = sizeof(T) == 4;
   using P = typename PlanPick<N, DGP_PLAN_P1>::type;
   using P2 = typename PlanPick<N, kF32 ? DGP_PLAN_P2_F32 : DGP_PLAN_P2_F64>::type;
-  // axis 2: a row's transform stays inside one wavefront (N/R <= 64): radix 8 from N = 512 on
-  using P3 = typename PlanPick<N, kF32 ? (N >= 512 ? 0 : DGP_PLAN_P3_F32) : DGP_PLAN_P3_F64>::type;
+  using P3 = typename PlanPick<N, kF32 ? DGP_PLAN_P3_F32 : DGP_PLAN_P3_F64>::type;
   static constexpr int R = P::R;
   static constexpr int kP1 = P1Tile<T, N, R>::kThreads;
   static constexpr int kP2 = ColTile<T, N, P2::R>::kThreads;
