@@ -81,6 +81,31 @@ def test_solve_same_sequence_fp64(dgp, iters):
         assert abs(info[0]["resid_min"] - min(info_ref.history)) <= 1e-10 * min(info_ref.history) + 1e-15
 
 
+@pytest.mark.parametrize("n", [8, 16, 64, 128])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_same_sequence_sizes(dgp, n, prec):
+    """Three updates from the linear guess at the mesh sizes the 32^3 case leaves out: each size
+    has its own tile shapes, radix plans and Nyquist indices in the axis-2, axis-1 (split Hessian)
+    and relaxation kernels.  Float64 to 1e-12 of the oracle; the float32 form to 1e-5."""
+    say("solve same-seq sizes", n, prec)
+    box = 2.0 * n
+    delta, lam = _c1(n, box, seed=40 + n)
+    op = oracle_params(lam=lam)
+    u_ref, info_ref = fld.solve(delta, box, op, fixed_iters=3)
+    with dgp.Plan(n, box, precision=prec) as plan:
+        p = gpu_params(dgp, lam=lam, tol=-1.0, max_iter=3)
+        u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        st, info = plan.solve_field(p, to_dev(delta), u)
+        torch.cuda.synchronize()
+        assert st == 0 and info[0]["iters"] == 3
+        if prec == 0:
+            assert np.max(np.abs(u.cpu().numpy() - u_ref)) <= 1e-12 * np.max(np.abs(u_ref))
+            hist, _ = plan.history()
+            assert np.max(np.abs(hist[:3] - np.asarray(info_ref.history[:3])) / np.asarray(info_ref.history[:3])) <= 1e-10
+        else:
+            assert rel_l2(u.cpu().numpy(), u_ref) <= 1e-5
+
+
 def test_solve_converged_fp64_c1(dgp):
     """32^3 log-normal (rms 1), screened (r_nl = 3), tolerance 1e-10 (config C1); plus C."""
     say("solve C1")
