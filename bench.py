@@ -374,12 +374,13 @@ def adjoint_bench(args, torch, dgp, inputs, dev):
     iters = [i["iters"] for i in info]
     evals = [i["passes"] for i in info]
     hs, n3 = (n // 2 + 1) * n * n, n ** 3
-    # algorithmic bytes of one iteration of one element: axis-1 forward of six spectra (12 hs),
-    # combine (6 in, 1 out), axis-1 inverse (2 hs); the fused axis-0 step reads the combined
-    # spectrum and nine real fields (mu, u, g, five Hessians), writes mu' and six spectra.
-    # Elements stop at their own iteration counts; the setup (Hessians of u*, the first
-    # products) and the final S mu transform are in the time but not in these bytes.
-    it_bytes = (12 + 7 + 2 + 1 + 6) * hs * 16 + (9 + 1) * n3 * 8
+    # algorithmic bytes of one iteration of one element: axis-1 forward of the six product
+    # spectra summed into three groups (6 in, 3 out), the combine (3 in, 1 out), axis-1 inverse
+    # (2 hs); the fused axis-0 step reads the combined spectrum and nine real fields (mu, u, g,
+    # five Hessians), writes mu' and six spectra.  Elements stop at their own iteration counts;
+    # the setup (Hessians of u*, the first products) and the final S mu transform are in the time
+    # but not in these bytes.
+    it_bytes = (9 + 4 + 2 + 1 + 6) * hs * 16 + (9 + 1) * n3 * 8
     total = it_bytes * sum(evals)
     out = {"mode": "adjoint", "config": {"workload": "implicit adjoint of 8 batched 128^3 log-normal fields "
                                                      "(sigma 0.3/1/3), float64, backward to 1e-12",

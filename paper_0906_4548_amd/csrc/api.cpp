@@ -1148,9 +1148,9 @@ static int hessians(dgp_plan* pl, const dgp_params* p, const double* u, double* 
   const size_t fs = (size_t)B * pl->hs, bn = (size_t)B * pl->n3;
   const SpecCoef cf = spec_coef(pl, p);
   TRY(fwd3<double>(pl, u, pl->spec_u, B, nullptr, s));
-  launch_p3<double>(n, SPEC_FANOUT6, pl->spec_u, fs, 1, pl->spec6, fs, 6, B, cf, nullptr, nullptr, pl->mean_u, nullptr,
+  launch_p3<double>(n, SPEC_HSPLIT, pl->spec_u, fs, 1, pl->spec6, fs, 3, B, cf, nullptr, nullptr, pl->mean_u, nullptr,
                     s);
-  launch_p2<double>(n, pl->spec6, 6, B, +1, nullptr, s);
+  launch_p2_split<double>(n, pl->spec6, fs, B, nullptr, s);
   for (int f = 0; f < 5; ++f) launch_p1_inv<double>(n, pl->spec6 + f * fs, H5 + f * bn, B, nullptr, s);
   LAUNCHCHK();
   return DGP_OK;
@@ -1217,8 +1217,8 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
   while (enqueued < limit) {
     const int m = std::min(chunk, limit - enqueued);
     for (int j = 0; j < m; ++j) {
-      launch_p2<double>(n, pl->spec6, 6, B, -1, pl->adj_ctl, s);
-      launch_p3<double>(n, SPEC_ADJ_COMBINE, pl->spec6, fs, 6, pl->spec_u, fs, 1, B, cf, nullptr, nullptr, nullptr,
+      launch_p2_adj_split(n, pl->spec6, fs, B, cf.lam2, pl->adj_ctl, s);
+      launch_p3<double>(n, SPEC_ADJ_COMBINE3, pl->spec6, fs, 3, pl->spec_u, fs, 1, B, cf, nullptr, nullptr, nullptr,
                         pl->adj_ctl, s);
       launch_p2<double>(n, pl->spec_u, 1, B, +1, pl->adj_ctl, s);
       launch_adj_step(n, true, pl->spec_u, MU, bn, u_star, H5, grad_u, pl->mean_u, pl->adj_vec, pl->spec6, fs,

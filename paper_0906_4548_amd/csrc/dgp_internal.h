@@ -11,19 +11,18 @@ namespace dgp {
 // Spectral multiplier modes of the axis-2 pass (forward FFT of each input row,
 // per-mode combination, inverse FFT of each output row).
 enum SpecMode : int {
-  SPEC_FANOUT6 = 0,   // u(k) -> 5 Hessian components (00,11,01,02,12) and sqrt(-lap)C = -u/kbar
   SPEC_SOURCE = 1,    // delta(k) -> S(k) = A(1 - beta/kbar) delta, u_lin(k) = S/(alpha - gamma/kbar)
   SPEC_CFIELD = 2,    // u(k) -> C(k) = -u/kbar^2
   SPEC_FORCES = 3,    // delta(k)[, u(k)] -> g_i = -(c/H0)^2 i k_i phi(k), i = 0..2 [, phi(k)]
   SPEC_POWER = 4,     // f(k) -> per-bin sums of |f|^2 (no outputs); optional 1/kbar^2 weight
   SPEC_POWER_GRAD = 5,// f(k) -> per-bin coefficient * f(k) [* 1/kbar^4]
-  SPEC_ADJ_COMBINE = 6,// 6 inputs (products with mu) -> one combined spectrum
+  SPEC_ADJ_COMBINE3 = 6,// the three group sums of launch_p2_adj_split -> one combined spectrum
   SPEC_COPY = 7,      // identity (plain forward+inverse round trip, for tests)
   SPEC_FWD_ONLY = 8,  // forward axis-2 transform only (spectrum export)
   SPEC_INV_ONLY = 9,  // inverse axis-2 transform only, times 1/N^3 (spectrum import)
   SPEC_HSPLIT = 10,   // u(k) -> C' = u/|n|^2, i n2 C' and -u/kbar into slots 0, 3 and 5 of the six
-                      // relaxation fields; the axis-1 pass (launch_p2_split) applies the axis-1
-                      // and axis-0 factors of the Hessian multipliers
+                      // relaxation fields (h00, h11, h01, h02, h12 and the nonlocal term after the
+                      // axis-1 pass launch_p2_split, which applies the axis-1 and axis-0 factors)
 };
 
 enum ForceMode : int { FORCE_NLDGP = 0, FORCE_LDGP = 1, FORCE_GRH = 2, FORCE_GR = 3 };
@@ -155,6 +154,10 @@ void launch_p2(int n, cx<T>* data, int nf, int batch, int dir, const SolveCtl* c
 // index of d)
 template <typename T>
 void launch_p2_split(int n, cx<T>* data, size_t fstride, int batch, const SolveCtl* ctl, hipStream_t s);
+// forward axis-1 pass of the adjoint's combine: six product spectra (axis-0 transformed) -> the
+// three group sums in slots 0, 3, 5, with the axis-1 and axis-0 factors and the 2 lam weights
+void launch_p2_adj_split(int n, cx<double>* data, size_t fstride, int batch, double lam2, const SolveCtl* ctl,
+                         hipStream_t s);
 // axis-2 pass: nin input arrays (each [batch][H][N][N]) -> nout output arrays
 template <typename T>
 void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out,

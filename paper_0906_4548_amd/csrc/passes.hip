@@ -294,6 +294,67 @@ k_p2_split(cx<T>* __restrict__ data, size_t fstride, int batch, const cx<T>* __r
   }
 }
 
+// Transposed split for the implicit adjoint's combine (float64): forward axis-1 transform of the
+// six product spectra (axis-0 transformed by the adjoint step), each times the axis-1 and axis-0
+// factors of its Hessian multiplier and its weight (2 lam on the diagonal terms, 4 lam on the
+// off-diagonal ones: the pair ij and ji), summed per group into slots 0, 3 and 5:
+//   0 <- 2 lam (n0^2 f0 + n1^2 f1 + 2 n0 n1 f2);  3 <- 4 lam (n0 f3 + n1 f4);  5 <- f5;
+// a factor odd in n_d is 0 at the Nyquist index of d.  SPEC_ADJ_COMBINE3 applies the rest
+// (1/|n|^2, n2/|n|^2, gamma/kbar).  A workgroup takes one column tile of one group; the sum is
+// stored over the group's first input after every input tile has been read.
+template <int N>
+__global__ void __launch_bounds__((P2SGeo<double, N>::G::kThreads))
+k_p2_adj_split(cx<double>* __restrict__ data, size_t fstride, int batch, double lam2,
+               const cx<double>* __restrict__ tw, const SolveCtl* __restrict__ ctl) {
+  using T = double;
+  using P = typename P2SGeo<T, N>::P;
+  constexpr int R = P::R;
+  using G = typename P2SGeo<T, N>::G;
+  constexpr int TY = G::kTY, TT = G::kT, H = N / 2 + 1;
+  const int role = blockIdx.z / batch, b = blockIdx.z % batch;
+  if (batch_done(ctl, b)) return;
+  const int k0 = blockIdx.y;
+  const int c = threadIdx.x % TY;
+  int t = threadIdx.x / TY;
+  __shared__ cx<T> lds[N * TY];
+  const int slot = role == 0 ? 0 : role == 1 ? 3 : 5;
+  const size_t off = ((size_t)b * H + k0) * N * N + blockIdx.x * TY + c;
+  const T n0 = T(k0);
+  const bool q0 = k0 == N / 2;
+  LdsCol<T, TY> L{lds, c};
+  cx<T> acc[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) acc[q] = mk(T(0), T(0));
+#pragma unroll 1
+  for (int i = 0; i < 3 - role; ++i) {
+    const cx<T>* twq = tw;
+    asm volatile("" : "+s"(twq), "+v"(t));
+    const int f = slot + i;
+    const cx<T>* src = data + f * fstride + off;
+    cx<T> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = src[(size_t)(t + q * TT) * N];
+    fft<T, N, P, -1>(v, twq, L, t);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k1 = t + q * TT;
+      const T n1 = T(k1 < N / 2 ? k1 : k1 - N);
+      const bool q1 = k1 == N / 2;
+      T m;
+      if (f == 0) m = lam2 * n0 * n0;
+      else if (f == 1) m = lam2 * n1 * n1;
+      else if (f == 2) m = (q0 || q1) ? T(0) : T(2) * lam2 * n0 * n1;
+      else if (f == 3) m = q0 ? T(0) : T(2) * lam2 * n0;
+      else if (f == 4) m = q1 ? T(0) : T(2) * lam2 * n1;
+      else m = T(1);
+      acc[q] = acc[q] + scale(v[q], m);
+    }
+  }
+  cx<T>* dst = data + slot * fstride + off;
+#pragma unroll
+  for (int q = 0; q < R; ++q) dst[(size_t)(t + q * TT) * N] = acc[q];
+}
+
 // ------------------------------------------------------------------ axis 2 with spectral multipliers
 struct Mode3 {
   int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
@@ -409,13 +470,16 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
       dstp[cf.nbins + bb] = cnt;
     }
     return;
-  } else if constexpr (MODE == SPEC_ADJ_COMBINE) {
+  } else if constexpr (MODE == SPEC_ADJ_COMBINE3) {
+    // the three group sums of k_p2_adj_split (slots 0, 3, 5: the axis-1 and axis-0 factors and
+    // the 2 lam weights applied) times the rest of each multiplier: 1/|n|^2, n2/|n|^2 (0 at the
+    // Nyquist index of axis 2) and gamma/kbar
     cx<T> acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = mk(T(0), T(0));
 #pragma unroll 1
-    for (int f = 0; f < 6; ++f) {
-      load_row(in + f * in_stride);
+    for (int g = 0; g < 3; ++g) {
+      load_row(in + (g == 0 ? 0 : g == 1 ? 3 : 5) * in_stride);
       fft<T, N, P, -1>(v, tw, L, t);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -423,11 +487,8 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
         if (m.msq == 0) continue;
         const double ik2 = 1.0 / double(m.msq);
         double mult;
-        if (f == 0) mult = cf.lam2 * double(m.n0) * double(m.n0) * ik2;
-        else if (f == 1) mult = cf.lam2 * double(m.n1) * double(m.n1) * ik2;
-        else if (f == 2) mult = (m.q0 || m.q1) ? 0.0 : 2.0 * cf.lam2 * double(m.n0) * double(m.n1) * ik2;
-        else if (f == 3) mult = (m.q0 || m.q2) ? 0.0 : 2.0 * cf.lam2 * double(m.n0) * double(m.n2) * ik2;
-        else if (f == 4) mult = (m.q1 || m.q2) ? 0.0 : 2.0 * cf.lam2 * double(m.n1) * double(m.n2) * ik2;
+        if (g == 0) mult = ik2;
+        else if (g == 1) mult = m.q2 ? 0.0 : double(m.n2) * ik2;
         else mult = cf.gamma / (cf.kappa * kf * sqrt(double(m.msq)));
         const T mm = T(mult * cf.inv_n3);
         acc[q] = acc[q] + scale(v[q], mm);
@@ -452,7 +513,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
         for (int q = 0; q < R; ++q) { v2[q] = v[q]; v[q] = keep[q]; }
       }
     }
-    if constexpr (MODE == SPEC_FANOUT6 || MODE == SPEC_HSPLIT) {
+    if constexpr (MODE == SPEC_HSPLIT) {
       if (valid && k0 == 0 && k1 == 0 && t == 0 && mean_out != nullptr) mean_out[b] = double(v[0].x) * cf.inv_n3;
     }
     if constexpr (MODE == SPEC_HSPLIT) {
@@ -505,7 +566,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
       }
       return;
     }
-    constexpr int NOUT = (MODE == SPEC_FANOUT6) ? 6 : (MODE == SPEC_SOURCE) ? 2 : (MODE == SPEC_FORCES) ? 4 : 1;
+    constexpr int NOUT = (MODE == SPEC_SOURCE) ? 2 : (MODE == SPEC_FORCES) ? 4 : 1;
 #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
       if constexpr (MODE == SPEC_FORCES) {
@@ -521,16 +582,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
           const double ik2 = 1.0 / ms;
           const double kb = cf.kappa * kf * sqrt(ms);
           const double ikb = 1.0 / kb;
-          if constexpr (MODE == SPEC_FANOUT6) {
-            double mult;
-            if (o == 0) mult = double(m.n0) * double(m.n0) * ik2;
-            else if (o == 1) mult = double(m.n1) * double(m.n1) * ik2;
-            else if (o == 2) mult = (m.q0 || m.q1) ? 0.0 : double(m.n0) * double(m.n1) * ik2;
-            else if (o == 3) mult = (m.q0 || m.q2) ? 0.0 : double(m.n0) * double(m.n2) * ik2;
-            else if (o == 4) mult = (m.q1 || m.q2) ? 0.0 : double(m.n1) * double(m.n2) * ik2;
-            else mult = -ikb;
-            res = scale(v[q], T(mult * cf.inv_n3));
-          } else if constexpr (MODE == SPEC_SOURCE) {
+          if constexpr (MODE == SPEC_SOURCE) {
             const double s = cf.A * (1.0 - cf.beta * ikb);
             const double mult = (o == 0) ? s : s / (cf.alpha - cf.gamma * ikb);
             res = scale(v[q], T(mult * cf.inv_n3));
@@ -618,6 +670,13 @@ static void p2_split_n(cx<T>* data, size_t fstride, int batch, const SolveCtl* c
   dim3 grid(N / G::kTY, N / 2 + 1, 3 * batch);
   hipLaunchKernelGGL((k_p2_split<T, N>), grid, dim3(G::kThreads), 0, s, data, fstride, batch, tw, ctl);
 }
+template <int N>
+static void p2_adj_split_n(cx<double>* data, size_t fstride, int batch, double lam2, const SolveCtl* ctl,
+                           const cx<double>* tw, hipStream_t s) {
+  using G = typename P2SGeo<double, N>::G;
+  dim3 grid(N / G::kTY, N / 2 + 1, 3 * batch);
+  hipLaunchKernelGGL((k_p2_adj_split<N>), grid, dim3(G::kThreads), 0, s, data, fstride, batch, lam2, tw, ctl);
+}
 template <typename T, int N>
 static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t os, int batch, const SpecCoef& cf,
                  const double* bc, double* bp, double* mean, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
@@ -627,13 +686,12 @@ static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t o
   dim3 blk(G::kThreads);
 #define DGP_P3(M) hipLaunchKernelGGL((k_p3<T, N, M>), grid, blk, 0, s, in, is, out, os, tw, cf, bc, bp, mean, ctl)
   switch (mode) {
-    case SPEC_FANOUT6: DGP_P3(SPEC_FANOUT6); break;
     case SPEC_SOURCE: DGP_P3(SPEC_SOURCE); break;
     case SPEC_CFIELD: DGP_P3(SPEC_CFIELD); break;
     case SPEC_FORCES: DGP_P3(SPEC_FORCES); break;
     case SPEC_POWER: DGP_P3(SPEC_POWER); break;
     case SPEC_POWER_GRAD: DGP_P3(SPEC_POWER_GRAD); break;
-    case SPEC_ADJ_COMBINE: DGP_P3(SPEC_ADJ_COMBINE); break;
+    case SPEC_ADJ_COMBINE3: DGP_P3(SPEC_ADJ_COMBINE3); break;
     case SPEC_COPY: DGP_P3(SPEC_COPY); break;
     case SPEC_FWD_ONLY: DGP_P3(SPEC_FWD_ONLY); break;
     case SPEC_INV_ONLY: DGP_P3(SPEC_INV_ONLY); break;
@@ -688,6 +746,13 @@ template <typename T>
 void launch_p2_split(int n, cx<T>* data, size_t fstride, int batch, const SolveCtl* ctl, hipStream_t s) {
   const cx<T>* tw = twiddles<T>(n);
 #define C(NN) p2_split_n<T, NN>(data, fstride, batch, ctl, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+void launch_p2_adj_split(int n, cx<double>* data, size_t fstride, int batch, double lam2, const SolveCtl* ctl,
+                         hipStream_t s) {
+  const cx<double>* tw = twiddles<double>(n);
+#define C(NN) p2_adj_split_n<NN>(data, fstride, batch, lam2, ctl, tw, s)
   DGP_DISPATCH_N(n, C)
 #undef C
 }
