@@ -777,10 +777,11 @@ static int deposit_impl(dgp_plan* pl, const void* pos, int fp32, long long np, l
   launch_zero_flag(pl->flag, s);
   launch_deposit(pl->n, pl->box, pos, fp32, np, grid, pl->flag, s);
   if (delta) {
-    launch_counts_to_delta(pl->n, grid, np, delta, pl->flag, s);
-    if (remove_mean) {
-      launch_absmean<double>(pl->n3, delta, 1, pl->red, nullptr, pl->vec, s);
-      launch_sub_mean(pl->n3, delta, 1, pl->vec, s);
+    if (remove_mean) {   // the mean of the counts (deterministic reduction), removed in the same pass
+      launch_absmean<long long>(pl->n3, grid, 1, pl->red, nullptr, pl->vec, s);
+      launch_counts_to_delta(pl->n, grid, np, delta, pl->flag, s, pl->vec);
+    } else {
+      launch_counts_to_delta(pl->n, grid, np, delta, pl->flag, s);
     }
   }
   LAUNCHCHK();
@@ -938,9 +939,8 @@ extern "C" int dgp_deposit_noalloc(int n, double box, const void* pos, int pos_i
   launch_fill_zero(grid_fixed, n3, s);
   launch_zero_flag(flag, s);
   launch_deposit(n, box, pos, pos_is_fp32, np, grid_fixed, flag, s);
-  launch_counts_to_delta(n, grid_fixed, np, delta, flag, s);
-  launch_absmean<double>(n3, delta, 1, sc, nullptr, mean, s);
-  launch_sub_mean(n3, delta, 1, mean, s);
+  launch_absmean<long long>(n3, grid_fixed, 1, sc, nullptr, mean, s);
+  launch_counts_to_delta(n, grid_fixed, np, delta, flag, s, mean);
   LAUNCHCHK();
   return DGP_OK;
 }

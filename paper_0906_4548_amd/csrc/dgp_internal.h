@@ -235,8 +235,10 @@ void launch_nonelliptic(size_t n3, int batch, const double* u, const double* h5,
 void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long np, long long* grid, int* bad,
                     hipStream_t s);
 // delta = Q 2^-40 N^3/np - 1 (NaN everywhere when *bad is set)
-void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s);
-void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s);
+// delta from the fixed-point counts; mean_q (optional, device): the mean of the counts, whose delta
+// value is subtracted in the same pass (mean removal)
+void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s,
+                            const double* mean_q = nullptr);
 // zero `words` 8-byte words (a fill kernel: no memset node in captured streams)
 void launch_fill_zero(void* p, size_t words, hipStream_t s);
 void launch_zero_flag(int* bad, hipStream_t s);

@@ -225,23 +225,18 @@ k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsi
   }
 }
 
+// delta = counts * qscale - 1; with mean_q (the mean of the fixed-point counts, a deterministic
+// reduction of the grid), minus the mean of delta, qscale <q> - 1, in the same pass
 __global__ void __launch_bounds__(256)
 k_counts_to_delta(const long long* __restrict__ grid, size_t n3, double qscale, double* __restrict__ delta,
-                  const int* __restrict__ bad) {
+                  const int* __restrict__ bad, const double* __restrict__ mean_q) {
 #pragma clang fp contract(off)
   const bool nan_out = *bad != 0;   // a non-finite position: delta is undefined, mark it so
+  const double m = mean_q ? *mean_q * qscale - 1.0 : 0.0;
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
     const double d = double(grid[i]) * qscale;
-    delta[i] = nan_out ? __builtin_nan("") : d - 1.0;
+    delta[i] = nan_out ? __builtin_nan("") : (d - 1.0) - m;
   }
-}
-
-__global__ void __launch_bounds__(256)
-k_sub_mean(double* __restrict__ x, size_t n3, const double* __restrict__ mean) {
-  const int b = blockIdx.y;
-  const double m = mean[b];
-  double* xb = x + (size_t)b * n3;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) xb[i] -= m;
 }
 
 // CIC interpolation of an NC-component field: f[k] = sum over the 8 corners of
@@ -609,10 +604,11 @@ void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long 
                        scale, out, bad);
 }
 
-void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s) {
+void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s,
+                            const double* mean_q) {
   const size_t n3 = (size_t)n * n * n;
   const double qscale = ldexp(double(n3) / double(np), -40);
-  hipLaunchKernelGGL(k_counts_to_delta, dim3(grid_strided(n3)), dim3(256), 0, s, grid, n3, qscale, delta, bad);
+  hipLaunchKernelGGL(k_counts_to_delta, dim3(grid_strided(n3)), dim3(256), 0, s, grid, n3, qscale, delta, bad, mean_q);
 }
 
 void launch_fill_zero(void* p, size_t words, hipStream_t s) {
@@ -620,9 +616,6 @@ void launch_fill_zero(void* p, size_t words, hipStream_t s) {
                      words);
 }
 
-void launch_sub_mean(size_t n3, double* x, int batch, const double* mean, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_mean, dim3(grid_strided(n3), batch), dim3(256), 0, s, x, n3, mean);
-}
 
 template <typename M, int NC>
 static void interp_m(int n, double box, const M* mesh, const void* pos, int pos_fp32, long long np, double* out,

@@ -1074,5 +1074,6 @@ template void launch_relax<float>(int, const cx<float>*, float*, const float*, c
                                   hipEvent_t);
 template void launch_absmean<double>(size_t, const double*, int, double*, double*, double*, hipStream_t);
 template void launch_absmean<float>(size_t, const float*, int, double*, double*, double*, hipStream_t);
+template void launch_absmean<long long>(size_t, const long long*, int, double*, double*, double*, hipStream_t);
 
 }  // namespace dgp
