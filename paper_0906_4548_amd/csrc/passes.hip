@@ -566,12 +566,89 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
       }
       return;
     }
-    constexpr int NOUT = (MODE == SPEC_SOURCE) ? 2 : (MODE == SPEC_FORCES) ? 4 : 1;
+    if constexpr (MODE == SPEC_FORCES) {
+      // phi(k) once per mode, times 1/N^3 (0 at k = 0); each output then takes its own factor:
+      // g_d = -(c/H0)^2 (i k_d) phi with k_d = 0 at the Nyquist index of d, and phi itself
+      cx<T> ph[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        ph[q] = mk(T(0), T(0));
+        if (m.msq != 0) {
+          const double ms = double(m.msq);
+          const double kb = cf.kappa * kf * sqrt(ms);
+          const double ikb = 1.0 / kb;
+          // phi(k) from the modified Poisson equation (or its linear / GR forms)
+          const double dr = double(v[q].x), di = double(v[q].y);
+          double nr, ni, den;
+          if (cf.force_mode == FORCE_GRH || cf.force_mode == FORCE_GR) {   // Eq. GRPoisson (kappa, om15 of the run's background)
+            nr = cf.om15 * dr; ni = cf.om15 * di; den = kb * kb;
+          } else {
+            double ur, ui;
+            if (cf.force_mode == FORCE_NLDGP) {
+              ur = double(v2[q].x); ui = double(v2[q].y);
+            } else {   // linear solution from delta
+              const double sl = cf.A * (1.0 - cf.beta * ikb) / (cf.alpha - cf.gamma * ikb);
+              ur = sl * dr; ui = sl * di;
+            }
+            const double cu = -cf.inv2eta + cf.c2 * ikb;
+            nr = cf.om15 * dr + cu * ur;
+            ni = cf.om15 * di + cu * ui;
+            den = kb * kb + kb * cf.inv_eta_nl;
+          }
+          ph[q] = mk(T(-nr / den * cf.inv_n3), T(-ni / den * cf.inv_n3));
+        }
+      }
+      const int nout = cf.with_phi ? 4 : 3;
+#pragma unroll 1
+      for (int o = 0; o < nout; ++o) {
+        cx<T> w[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          if (o == 3) {
+            w[q] = ph[q];
+          } else {
+            const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+            const int nd = (o == 0) ? m.n0 : (o == 1) ? m.n1 : m.n2;
+            const bool nq = (o == 0) ? m.q0 : (o == 1) ? m.q1 : m.q2;
+            const T f = nq ? T(0) : T(cf.force_scale * kf * double(nd));   // (c/H0)^2 k_d
+            w[q] = mk(f * ph[q].y, -f * ph[q].x);
+          }
+        }
+        fft<T, N, P, +1>(w, tw, L, t);
+        store_row(out + o * out_stride, w);
+      }
+      return;
+    }
+    if constexpr (MODE == SPEC_SOURCE) {
+      // the two multipliers once per mode, times 1/N^3 (0 at k = 0): S = A (1 - beta/kbar) delta
+      // and the linear solution S / (alpha - gamma/kbar)
+      T m0[R], m1[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const Mode3 m = mode_of(N, k0, k1, t + q * TT);
+        m0[q] = T(0);
+        m1[q] = T(0);
+        if (m.msq != 0) {
+          const double ikb = 1.0 / (cf.kappa * kf * sqrt(double(m.msq)));
+          const double sv = cf.A * (1.0 - cf.beta * ikb);
+          m0[q] = T(sv * cf.inv_n3);
+          m1[q] = T(sv / (cf.alpha - cf.gamma * ikb) * cf.inv_n3);
+        }
+      }
+#pragma unroll 1
+      for (int o = 0; o < 2; ++o) {
+        cx<T> w[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) w[q] = scale(v[q], o ? m1[q] : m0[q]);
+        fft<T, N, P, +1>(w, tw, L, t);
+        store_row(out + o * out_stride, w);
+      }
+      return;
+    }
+    constexpr int NOUT = 1;
 #pragma unroll 1
     for (int o = 0; o < NOUT; ++o) {
-      if constexpr (MODE == SPEC_FORCES) {
-        if (o == 3 && !cf.with_phi) break;
-      }
       cx<T> w[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -582,11 +659,7 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
           const double ik2 = 1.0 / ms;
           const double kb = cf.kappa * kf * sqrt(ms);
           const double ikb = 1.0 / kb;
-          if constexpr (MODE == SPEC_SOURCE) {
-            const double s = cf.A * (1.0 - cf.beta * ikb);
-            const double mult = (o == 0) ? s : s / (cf.alpha - cf.gamma * ikb);
-            res = scale(v[q], T(mult * cf.inv_n3));
-          } else if constexpr (MODE == SPEC_CFIELD) {
+          if constexpr (MODE == SPEC_CFIELD) {
             res = scale(v[q], T(-ikb * ikb * cf.inv_n3));
           } else if constexpr (MODE == SPEC_COPY) {
             res = scale(v[q], T(cf.inv_n3));
@@ -603,36 +676,6 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
               if (cf.power_c) coef *= (ikb * ikb) * (ikb * ikb);
             }
             res = scale(v[q], T(coef * cf.inv_n3));
-          } else if constexpr (MODE == SPEC_FORCES) {
-            // phi(k) from the modified Poisson equation (or its linear / GR forms)
-            const double dr = double(v[q].x), di = double(v[q].y);
-            double nr, ni, den;
-            if (cf.force_mode == FORCE_GRH || cf.force_mode == FORCE_GR) {   // Eq. GRPoisson (kappa, om15 of the run's background)
-              nr = cf.om15 * dr; ni = cf.om15 * di; den = kb * kb;
-            } else {
-              double ur, ui;
-              if (cf.force_mode == FORCE_NLDGP) {
-                ur = double(v2[q].x); ui = double(v2[q].y);
-              } else {   // linear solution from delta
-                const double s = cf.A * (1.0 - cf.beta * ikb) / (cf.alpha - cf.gamma * ikb);
-                ur = s * dr; ui = s * di;
-              }
-              const double cu = -cf.inv2eta + cf.c2 * ikb;
-              nr = cf.om15 * dr + cu * ur;
-              ni = cf.om15 * di + cu * ui;
-              den = kb * kb + kb * cf.inv_eta_nl;
-            }
-            const double pr = -nr / den, pi = -ni / den;
-            if (o < 3) {
-              const int nd = (o == 0) ? m.n0 : (o == 1) ? m.n1 : m.n2;
-              const bool nq = (o == 0) ? m.q0 : (o == 1) ? m.q1 : m.q2;
-              const double kd = nq ? 0.0 : kf * double(nd);
-              // g = -(c/H0)^2 (i k_d) phi
-              const double sc = -cf.force_scale * kd * cf.inv_n3;
-              res = mk(T(-sc * pi), T(sc * pr));
-            } else {
-              res = mk(T(pr * cf.inv_n3), T(pi * cf.inv_n3));
-            }
           }
         }
         w[q] = res;
