@@ -448,7 +448,6 @@ static SpecCoef spec_coef(const dgp_plan* pl, const dgp_params* p) {
   c.inv_n3 = 1.0 / double(pl->n3);
   c.lam2 = 2.0 * p->lambda;
   c.force_mode = p->force_mode;
-  c.with_phi = 0;
   c.power_c = 0;
   c.nbins = 64;
   return c;
@@ -809,14 +808,12 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
   const int n = pl->n;
   const size_t fs = pl->hs, n3 = pl->n3;
   SpecCoef cf = spec_coef(pl, p);
-  cf.with_phi = phi_n ? 1 : 0;
   if (p->force_mode == DGP_FORCE_GR) {   // Eq. GRPoisson in the LCDM background: kbar = c k/(a H), (3/2) Omega_m(a)
     const double e = hubble_E_lcdm(p->omega_m0, p->a);
     cf.kappa = kCOverH0 / (p->a * e);
     cf.om15 = 1.5 * p->omega_m0 / (p->a * p->a * p->a * e * e);
   }
   const bool use_u = p->force_mode == DGP_FORCE_NLDGP;
-  const int nout = phi_n ? 4 : 3;
   if (pl->precision == DGP_FP32) {
     cx<float>* fin = pl->spec6_32 + 6 * fs;   // delta, then u
     float* tmp = pl->U32;                     // the solve's float32 iterates are free here
@@ -829,9 +826,9 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
       launch_p2<float>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
     else if (use_u)
       launch_p2<float>(n, fin + fs, 1, 1, -1, nullptr, s);
-    launch_p3<float>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6_32, fs, nout, 1, cf, nullptr, nullptr, nullptr,
+    launch_p3<float>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6_32, fs, 2, 1, cf, nullptr, nullptr, nullptr,
                      nullptr, s);
-    launch_p2<float>(n, pl->spec6_32, nout, 1, +1, nullptr, s);
+    launch_p2_force_split<float>(n, pl->spec6_32, fs, 1, phi_n ? 1 : 0, cf.force_scale * cf.kf, s);
     launch_p1_inv<float>(n, pl->spec6_32, pl->mesh3_32, 3, nullptr, s);
     if (phi_n) {
       launch_p1_inv<float>(n, pl->spec6_32 + 3 * fs, tmp, 1, nullptr, s);
@@ -847,9 +844,9 @@ static int force_mesh(dgp_plan* pl, const dgp_params* p, const double* delta, co
     launch_p2<double>(n, fin, use_u ? 2 : 1, 1, -1, nullptr, s);
   else if (use_u)
     launch_p2<double>(n, fin + fs, 1, 1, -1, nullptr, s);
-  launch_p3<double>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6, fs, nout, 1, cf, nullptr, nullptr, nullptr,
+  launch_p3<double>(n, SPEC_FORCES, fin, fs, use_u ? 2 : 1, pl->spec6, fs, 2, 1, cf, nullptr, nullptr, nullptr,
                     nullptr, s);
-  launch_p2<double>(n, pl->spec6, nout, 1, +1, nullptr, s);
+  launch_p2_force_split<double>(n, pl->spec6, fs, 1, phi_n ? 1 : 0, cf.force_scale * cf.kf, s);
   launch_p1_inv<double>(n, pl->spec6, pl->mesh3, 3, nullptr, s);
   if (phi_n) launch_p1_inv<double>(n, pl->spec6 + 3 * fs, phi_n, 1, nullptr, s);
   LAUNCHCHK();

@@ -13,7 +13,7 @@ namespace dgp {
 enum SpecMode : int {
   SPEC_SOURCE = 1,    // delta(k) -> S(k) = A(1 - beta/kbar) delta, u_lin(k) = S/(alpha - gamma/kbar)
   SPEC_CFIELD = 2,    // u(k) -> C(k) = -u/kbar^2
-  SPEC_FORCES = 3,    // delta(k)[, u(k)] -> g_i = -(c/H0)^2 i k_i phi(k), i = 0..2 [, phi(k)]
+  SPEC_FORCES = 3,    // delta(k)[, u(k)] -> phi(k) (slot 0) and g_2 = -(c/H0)^2 i k_2 phi(k) (slot 2)
   SPEC_POWER = 4,     // f(k) -> per-bin sums of |f|^2 (no outputs); optional 1/kbar^2 weight
   SPEC_POWER_GRAD = 5,// f(k) -> per-bin coefficient * f(k) [* 1/kbar^4]
   SPEC_ADJ_COMBINE3 = 6,// the three group sums of launch_p2_adj_split -> one combined spectrum
@@ -40,7 +40,6 @@ struct SpecCoef {
   double inv_n3;    // 1/N^3 (inverse-transform normalisation, folded into the multiplier)
   double lam2;      // 2 lam (adjoint combine)
   int force_mode;   // ForceMode
-  int with_phi;     // FORCES: also output phi
   int power_c;      // POWER/POWER_GRAD: weight |f|^2 by 1/kbar^4 (spectrum of C from u)
   int nbins;        // POWER: number of bins
 };
@@ -158,6 +157,10 @@ void launch_p2_split(int n, cx<T>* data, size_t fstride, int batch, const SolveC
 // three group sums in slots 0, 3, 5, with the axis-1 and axis-0 factors and the 2 lam weights
 void launch_p2_adj_split(int n, cx<double>* data, size_t fstride, int batch, double lam2, const SolveCtl* ctl,
                          hipStream_t s);
+// axis-1 inverse pass of the force mesh: phi (slot 0) and g2 (slot 2) from the axis-2 pass ->
+// g0, g1, g2 in slots 0..2 and phi in slot 3 when with_phi; fk = (c/H0)^2 kf
+template <typename T>
+void launch_p2_force_split(int n, cx<T>* data, size_t fstride, int batch, int with_phi, double fk, hipStream_t s);
 // axis-2 pass: nin input arrays (each [batch][H][N][N]) -> nout output arrays
 template <typename T>
 void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out,

@@ -355,6 +355,53 @@ k_p2_adj_split(cx<double>* __restrict__ data, size_t fstride, int batch, double 
   for (int q = 0; q < R; ++q) dst[(size_t)(t + q * TT) * N] = acc[q];
 }
 
+// Axis-1 inverse pass of the force mesh: the axis-2 pass wrote phi to slot 0 and g2 to slot 2;
+// k0 is fixed per workgroup, so this pass forms g0 = -(c/H0)^2 (i k0) phi into slot 0 and
+// g1 = -(c/H0)^2 (i k1) phi into slot 1 (k_d = 0 at the Nyquist index of d), phi itself into slot 3
+// when asked for, and inverts g2 in place.  Role 0 holds its phi tile in registers across its
+// outputs (written in descending slots, the in-place one last); role 1 is a plain inverse.
+template <typename T, int N>
+__global__ void __launch_bounds__((P2SGeo<T, N>::G::kThreads))
+k_p2_force_split(cx<T>* __restrict__ data, size_t fstride, int batch, int with_phi, double fk,
+                 const cx<T>* __restrict__ tw) {
+  using P = typename P2SGeo<T, N>::P;
+  constexpr int R = P::R;
+  using G = typename P2SGeo<T, N>::G;
+  constexpr int TY = G::kTY, TT = G::kT, H = N / 2 + 1;
+  const int role = blockIdx.z / batch, b = blockIdx.z % batch;
+  const int k0 = blockIdx.y;
+  const int c = threadIdx.x % TY;
+  int t = threadIdx.x / TY;
+  __shared__ cx<T> lds[N * TY];
+  const int slot = role == 0 ? 0 : 2;
+  const size_t off = ((size_t)b * H + k0) * N * N + blockIdx.x * TY + c;
+  const cx<T>* src = data + slot * fstride + off;
+  const T f0 = k0 == N / 2 ? T(0) : T(fk * double(k0));   // (c/H0)^2 k0
+  LdsCol<T, TY> L{lds, c};
+  cx<T> v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = src[(size_t)(t + q * TT) * N];
+  // outputs of role 0: o = 2 phi (slot 3, when asked for), 1 g1 (slot 1), 0 g0 (slot 0)
+#pragma unroll 1
+  for (int o = role == 0 ? (with_phi ? 2 : 1) : 0; o >= 0; --o) {
+    const cx<T>* twq = tw;
+    asm volatile("" : "+s"(twq), "+v"(t));
+    cx<T> w[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k1 = t + q * TT;
+      T f = T(0);
+      if (role == 0 && o == 0) f = f0;
+      else if (role == 0 && o == 1) f = k1 == N / 2 ? T(0) : T(fk * double(k1 < N / 2 ? k1 : k1 - N));
+      w[q] = (role == 1 || o == 2) ? v[q] : mk(f * v[q].y, -f * v[q].x);
+    }
+    fft<T, N, P, +1>(w, twq, L, t);
+    cx<T>* dst = data + (role == 1 ? 2 : o == 2 ? 3 : o) * fstride + off;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[(size_t)(t + q * TT) * N] = w[q];
+  }
+}
+
 // ------------------------------------------------------------------ axis 2 with spectral multipliers
 struct Mode3 {
   int n0, n1, n2;        // signed mode numbers (n0 >= 0 on the half axis)
@@ -567,8 +614,8 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
       return;
     }
     if constexpr (MODE == SPEC_FORCES) {
-      // phi(k) once per mode, times 1/N^3 (0 at k = 0); each output then takes its own factor:
-      // g_d = -(c/H0)^2 (i k_d) phi with k_d = 0 at the Nyquist index of d, and phi itself
+      // phi(k) once per mode, times 1/N^3 (0 at k = 0); the force g_d = -(c/H0)^2 (i k_d) phi with
+      // k_d = 0 at the Nyquist index of d
       cx<T> ph[R];
 #pragma unroll
       for (int q = 0; q < R; ++q) {
@@ -599,24 +646,23 @@ k_p3(const cx<T>* __restrict__ in, size_t in_stride, cx<T>* __restrict__ out, si
           ph[q] = mk(T(-nr / den * cf.inv_n3), T(-ni / den * cf.inv_n3));
         }
       }
-      const int nout = cf.with_phi ? 4 : 3;
+      // two outputs: phi (slot 0; the axis-1 pass k_p2_force_split forms g0, g1 and phi from it)
+      // and g2 (slot 2), the gradient factor being a product of per-axis factors
 #pragma unroll 1
-      for (int o = 0; o < nout; ++o) {
+      for (int o = 0; o < 2; ++o) {
         cx<T> w[R];
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          if (o == 3) {
+          if (o == 0) {
             w[q] = ph[q];
           } else {
             const Mode3 m = mode_of(N, k0, k1, t + q * TT);
-            const int nd = (o == 0) ? m.n0 : (o == 1) ? m.n1 : m.n2;
-            const bool nq = (o == 0) ? m.q0 : (o == 1) ? m.q1 : m.q2;
-            const T f = nq ? T(0) : T(cf.force_scale * kf * double(nd));   // (c/H0)^2 k_d
+            const T f = m.q2 ? T(0) : T(cf.force_scale * kf * double(m.n2));   // (c/H0)^2 k_2
             w[q] = mk(f * ph[q].y, -f * ph[q].x);
           }
         }
         fft<T, N, P, +1>(w, tw, L, t);
-        store_row(out + o * out_stride, w);
+        store_row(out + 2 * o * out_stride, w);
       }
       return;
     }
@@ -721,6 +767,13 @@ static void p2_adj_split_n(cx<double>* data, size_t fstride, int batch, double l
   hipLaunchKernelGGL((k_p2_adj_split<N>), grid, dim3(G::kThreads), 0, s, data, fstride, batch, lam2, tw, ctl);
 }
 template <typename T, int N>
+static void p2_force_split_n(cx<T>* data, size_t fstride, int batch, int with_phi, double fk, const cx<T>* tw,
+                             hipStream_t s) {
+  using G = typename P2SGeo<T, N>::G;
+  dim3 grid(N / G::kTY, N / 2 + 1, 2 * batch);
+  hipLaunchKernelGGL((k_p2_force_split<T, N>), grid, dim3(G::kThreads), 0, s, data, fstride, batch, with_phi, fk, tw);
+}
+template <typename T, int N>
 static void p3_n(SpecMode mode, const cx<T>* in, size_t is, cx<T>* out, size_t os, int batch, const SpecCoef& cf,
                  const double* bc, double* bp, double* mean, const SolveCtl* ctl, const cx<T>* tw, hipStream_t s) {
   using G = RowTile<N, Geo<T, N>::P3::R>;
@@ -800,6 +853,13 @@ void launch_p2_adj_split(int n, cx<double>* data, size_t fstride, int batch, dou
 #undef C
 }
 template <typename T>
+void launch_p2_force_split(int n, cx<T>* data, size_t fstride, int batch, int with_phi, double fk, hipStream_t s) {
+  const cx<T>* tw = twiddles<T>(n);
+#define C(NN) p2_force_split_n<T, NN>(data, fstride, batch, with_phi, fk, tw, s)
+  DGP_DISPATCH_N(n, C)
+#undef C
+}
+template <typename T>
 void launch_p3(int n, SpecMode mode, const cx<T>* in, size_t in_stride, int nin, cx<T>* out, size_t out_stride,
                int nout, int batch, const SpecCoef& coef, const double* bin_coef, double* bin_partial,
                double* mean_out, const SolveCtl* ctl, hipStream_t s) {
@@ -831,6 +891,8 @@ template void launch_p2<double>(int, cx<double>*, int, int, int, const SolveCtl*
 template void launch_p2<float>(int, cx<float>*, int, int, int, const SolveCtl*, hipStream_t);
 template void launch_p2_split<double>(int, cx<double>*, size_t, int, const SolveCtl*, hipStream_t);
 template void launch_p2_split<float>(int, cx<float>*, size_t, int, const SolveCtl*, hipStream_t);
+template void launch_p2_force_split<double>(int, cx<double>*, size_t, int, int, double, hipStream_t);
+template void launch_p2_force_split<float>(int, cx<float>*, size_t, int, int, double, hipStream_t);
 template void launch_p3<double>(int, SpecMode, const cx<double>*, size_t, int, cx<double>*, size_t, int, int,
                                 const SpecCoef&, const double*, double*, double*, const SolveCtl*, hipStream_t);
 template void launch_p3<float>(int, SpecMode, const cx<float>*, size_t, int, cx<float>*, size_t, int, int,
