@@ -119,8 +119,24 @@ int dgp_params_init(dgp_params* p, double omega_m0, double a);
  * allocates its device workspace on the current device (hipMalloc) and frees it
  * in dgp_plan_destroy.  DGP_E_INVALID on bad sizes, DGP_E_NOMEM on allocation failure. */
 int dgp_plan_create(dgp_plan** plan, int n, int batch, double box, int precision);
+/* Device bytes a plan of these sizes uses: its buffers, each rounded up to 256 bytes, as
+ * dgp_plan_create allocates them (with_adjoint = 0), plus the buffers of the implicit adjoint
+ * that the first dgp_solve_field_backward or dgp_diagnostics call adds (with_adjoint != 0).
+ * A host-side computation (no device call).  Returns 0 for invalid sizes.  The per-device
+ * twiddle tables (shared by every plan, a few tens of KB) are not included. */
+size_t dgp_workspace_bytes(int n, int batch, int precision, int with_adjoint);
+/* dgp_plan_create on a caller-owned device workspace: every device buffer of the plan is carved
+ * from `workspace` (device memory on the current device, 256-byte aligned, at least
+ * dgp_workspace_bytes(n, batch, precision, 0) bytes; the caller keeps ownership and must keep
+ * it alive until dgp_plan_destroy).  With at least dgp_workspace_bytes(..., 1) bytes the
+ * adjoint's buffers come from it too; otherwise the first call that needs them returns
+ * DGP_E_INVALID.  The plan still allocates its small pinned host buffers and its events.
+ * DGP_E_INVALID on bad sizes, a NULL or misaligned workspace, or one that is too small. */
+int dgp_plan_create_ws(dgp_plan** plan, int n, int batch, double box, int precision, void* workspace,
+                       size_t workspace_bytes);
 int dgp_plan_destroy(dgp_plan* plan);
-/* Device bytes held by the plan. */
+/* Device bytes held by the plan (256-byte units; equal to dgp_workspace_bytes for the same
+ * sizes, with_adjoint once the adjoint's buffers exist). */
 size_t dgp_plan_device_bytes(const dgp_plan* plan);
 
 /* CIC mass assignment (Sec. III A, Eq. CIC), deterministic.

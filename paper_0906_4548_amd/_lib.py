@@ -12,7 +12,8 @@ DGP_INIT_LINEAR, DGP_INIT_ZERO, DGP_INIT_WARM = 0, 1, 2
 DGP_FORCE_NLDGP, DGP_FORCE_LDGP, DGP_FORCE_GRH, DGP_FORCE_GR = 0, 1, 2, 3
 
 EXPORTS = (
-    "dgp_params_init", "dgp_plan_create", "dgp_plan_destroy", "dgp_plan_device_bytes",
+    "dgp_params_init", "dgp_plan_create", "dgp_plan_create_ws", "dgp_workspace_bytes", "dgp_plan_destroy",
+    "dgp_plan_device_bytes",
     "dgp_deposit", "dgp_solve_field", "dgp_pm_forces", "dgp_step", "dgp_solve_field_backward",
     "dgp_deposit_backward", "dgp_deposit_noalloc", "dgp_interp", "dgp_interp_backward", "dgp_power_spectrum", "dgp_power_spectrum_backward",
     "dgp_fft_forward", "dgp_fft_inverse", "dgp_timing_enable", "dgp_timing_classes", "dgp_timing_read",
@@ -57,6 +58,9 @@ def load():
         "dgp_plan_create": (ctypes.c_int, [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]),
         "dgp_plan_destroy": (ctypes.c_int, [vp]),
         "dgp_plan_device_bytes": (ctypes.c_size_t, [vp]),
+        "dgp_plan_create_ws": (ctypes.c_int, [P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp,
+                                              ctypes.c_size_t]),
+        "dgp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "dgp_deposit": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_longlong, vp, vp, vp]),
         "dgp_solve_field": (ctypes.c_int, [vp, P(Params), vp, vp, vp, P(Info), vp]),
         "dgp_pm_forces": (ctypes.c_int, [vp, P(Params), vp, vp, vp, ctypes.c_int, ctypes.c_longlong, vp, vp, vp]),

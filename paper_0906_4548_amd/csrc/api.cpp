@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -225,6 +226,10 @@ struct dgp_plan {
   int* flag_host = nullptr;
   unsigned long long* fx_state = nullptr;
   std::vector<void*> dev_allocs;
+  // caller-owned device workspace (dgp_plan_create_ws): buffers are carved from it, 256-byte aligned
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_used = 0;
+  bool dry = false;   // size query (dgp_workspace_bytes): count the bytes, allocate nothing
   std::vector<void*> host_allocs;
   size_t bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -306,10 +311,26 @@ static void timing_flush(dgp_plan* pl) {
 template <typename T>
 static constexpr int tcls(int base) { return base + (sizeof(T) == 4 ? DGP_T_FP32_OFFSET : 0); }
 
+// Device buffer of `count` elements, accounted in 256-byte units: from the caller's workspace when
+// the plan has one, counted only in a size query, else hipMalloc.
 template <typename T>
 static int dalloc(dgp_plan* pl, T** ptr, size_t count) {
+  const size_t bytes = (sizeof(T) * (count ? count : 1) + 255) & ~size_t(255);
+  if (pl->dry) {
+    pl->bytes += bytes;
+    *ptr = nullptr;
+    return DGP_OK;
+  }
+  if (pl->ws) {
+    if (bytes > pl->ws_bytes - pl->ws_used)
+      return fail(DGP_E_INVALID, "caller workspace of %zu bytes is too small (%zu more needed at this point)",
+                  pl->ws_bytes, pl->ws_used + bytes - pl->ws_bytes);
+    *ptr = reinterpret_cast<T*>(pl->ws + pl->ws_used);
+    pl->ws_used += bytes;
+    pl->bytes += bytes;
+    return DGP_OK;
+  }
   void* p = nullptr;
-  const size_t bytes = sizeof(T) * (count ? count : 1);
   if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(DGP_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
@@ -322,6 +343,10 @@ static int dalloc(dgp_plan* pl, T** ptr, size_t count) {
 
 template <typename T>
 static int halloc(dgp_plan* pl, T** ptr, size_t count) {
+  if (pl->dry) {
+    *ptr = nullptr;
+    return DGP_OK;
+  }
   void* p = nullptr;
   if (hipHostMalloc(&p, sizeof(T) * (count ? count : 1), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -392,20 +417,33 @@ static int plan_alloc(dgp_plan* pl) {
   return DGP_OK;
 }
 
-extern "C" int dgp_plan_create(dgp_plan** out, int n, int batch, double box, int precision) {
-  if (!out) return fail(DGP_E_INVALID, "plan pointer is NULL");
-  *out = nullptr;
+static int check_plan_sizes(int n, int batch, double box, int precision) {
   if (n < 8 || n > 512 || (n & (n - 1)) != 0) return fail(DGP_E_INVALID, "N must be a power of two in [8, 512], got %d", n);
   if (batch < 1 || batch > 4096) return fail(DGP_E_INVALID, "batch must be in [1, 4096]");
   if (!(box > 0.0) || !std::isfinite(box)) return fail(DGP_E_INVALID, "box must be > 0");
   if (precision != DGP_FP64 && precision != DGP_FP32) return fail(DGP_E_INVALID, "bad precision");
-  dgp_plan* pl = new dgp_plan;
+  return DGP_OK;
+}
+
+static void plan_init(dgp_plan* pl, int n, int batch, double box, int precision) {
   pl->n = n;
   pl->batch = batch;
   pl->box = box;
   pl->precision = precision;
   pl->n3 = (size_t)n * n * n;
   pl->hs = (size_t)(n / 2 + 1) * n * n;
+}
+
+static int adj_alloc(dgp_plan* pl);
+
+static int plan_create(dgp_plan** out, int n, int batch, double box, int precision, void* ws, size_t ws_bytes) {
+  if (!out) return fail(DGP_E_INVALID, "plan pointer is NULL");
+  *out = nullptr;
+  TRY(check_plan_sizes(n, batch, box, precision));
+  dgp_plan* pl = new dgp_plan;
+  plan_init(pl, n, batch, box, precision);
+  pl->ws = static_cast<char*>(ws);
+  pl->ws_bytes = ws ? ws_bytes : 0;
   if (hipGetDevice(&pl->device) != hipSuccess) {
     delete pl;
     return fail(DGP_E_HIP, "hipGetDevice failed");
@@ -420,6 +458,34 @@ extern "C" int dgp_plan_create(dgp_plan** out, int n, int batch, double box, int
   }
   *out = pl;
   return DGP_OK;
+}
+
+extern "C" int dgp_plan_create(dgp_plan** out, int n, int batch, double box, int precision) {
+  return plan_create(out, n, batch, box, precision, nullptr, 0);
+}
+
+extern "C" size_t dgp_workspace_bytes(int n, int batch, int precision, int with_adjoint) {
+  if (check_plan_sizes(n, batch, 1.0, precision) != DGP_OK) return 0;
+  dgp_plan dry;
+  dry.dry = true;
+  plan_init(&dry, n, batch, 1.0, precision);
+  if (plan_alloc(&dry) != DGP_OK) return 0;
+  if (with_adjoint && adj_alloc(&dry) != DGP_OK) return 0;
+  return dry.bytes;
+}
+
+extern "C" int dgp_plan_create_ws(dgp_plan** out, int n, int batch, double box, int precision, void* workspace,
+                                  size_t workspace_bytes) {
+  if (!out) return fail(DGP_E_INVALID, "plan pointer is NULL");
+  *out = nullptr;
+  TRY(check_plan_sizes(n, batch, box, precision));
+  if (!workspace) return fail(DGP_E_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(DGP_E_INVALID, "workspace must be 256-byte aligned");
+  const size_t need = dgp_workspace_bytes(n, batch, precision, 0);
+  if (workspace_bytes < need)
+    return fail(DGP_E_INVALID, "workspace of %zu bytes is smaller than the %zu bytes this plan needs", workspace_bytes,
+                need);
+  return plan_create(out, n, batch, box, precision, workspace, workspace_bytes);
 }
 
 extern "C" int dgp_plan_destroy(dgp_plan* pl) {
@@ -1119,23 +1185,21 @@ int adjoint_solve(dgp_plan* pl, const dgp_params* p, const double* delta, const 
 // float64 work fields of the adjoint and the diagnostics, allocated on first use: [9][B][n3]
 // (five Hessians, three multiplier buffers, the returned multipliers), reduction scratch and
 // the adjoint's own control blocks (the forward solve's stay as its last solve left them)
-static int ensure_adj(dgp_plan* pl) {
-  if (pl->adj) return DGP_OK;
+// the adjoint's device buffers (Hessians of u*, multipliers, reductions, control blocks)
+static int adj_alloc(dgp_plan* pl) {
   const size_t bn = (size_t)pl->batch * pl->n3;
   TRY(dalloc(pl, &pl->adj, 9 * bn));
   const size_t red = std::max((size_t)adjoint_groups(pl->n3) * 2, (size_t)adj_step_groups(pl->n) * 3);
   TRY(dalloc(pl, &pl->adj_red, red * pl->batch));
   TRY(dalloc(pl, &pl->adj_vec, pl->batch));
-  void* d = nullptr;
-  if (hipMalloc(&d, sizeof(SolveCtl) * pl->batch) != hipSuccess) return fail(DGP_E_NOMEM, "adjoint control blocks");
-  pl->dev_allocs.push_back(d);
-  pl->adj_ctl = static_cast<SolveCtl*>(d);
-  void* h = nullptr;
-  if (hipHostMalloc(&h, sizeof(SolveCtl) * pl->batch, hipHostMallocDefault) != hipSuccess)
-    return fail(DGP_E_NOMEM, "adjoint control blocks (host)");
-  pl->host_allocs.push_back(h);
-  pl->adj_ctl_host = static_cast<SolveCtl*>(h);
+  TRY(dalloc(pl, &pl->adj_ctl, pl->batch));
+  TRY(halloc(pl, &pl->adj_ctl_host, pl->batch));
   return DGP_OK;
+}
+
+static int ensure_adj(dgp_plan* pl) {
+  if (pl->adj_ctl_host) return DGP_OK;
+  return adj_alloc(pl);
 }
 
 // h00, h11, h01, h02, h12 of u (H5: [5][B][n3]; h22 follows from the trace identity) and <u>

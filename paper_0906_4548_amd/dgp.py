@@ -48,13 +48,28 @@ def _ptr(t, dtype=None, numel=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
-class Plan:
-    """Workspace for an N^3 mesh of side ``box`` with ``batch`` fields in ``precision``."""
+def workspace_bytes(n, batch=1, precision=FP64, with_adjoint=False):
+    """Device bytes a plan of these sizes uses (dgp_workspace_bytes); 0 for invalid sizes."""
+    return int(_lib.load().dgp_workspace_bytes(int(n), int(batch), int(precision), 1 if with_adjoint else 0))
 
-    def __init__(self, n, box, batch=1, precision=FP64):
+
+class Plan:
+    """Workspace for an N^3 mesh of side ``box`` with ``batch`` fields in ``precision``.
+
+    ``workspace``: optional caller-owned device buffer (a CUDA tensor of at least
+    ``workspace_bytes(n, batch, precision)`` bytes, 256-byte aligned, as torch allocates); the
+    plan then carves its device buffers from it (dgp_plan_create_ws) and keeps a reference."""
+
+    def __init__(self, n, box, batch=1, precision=FP64, workspace=None):
         self.n, self.box, self.batch, self.precision = int(n), float(box), int(batch), int(precision)
         h = ctypes.c_void_p()
-        check(_lib.load().dgp_plan_create(ctypes.byref(h), self.n, self.batch, self.box, self.precision))
+        self._ws = workspace
+        if workspace is None:
+            check(_lib.load().dgp_plan_create(ctypes.byref(h), self.n, self.batch, self.box, self.precision))
+        else:
+            nbytes = workspace.numel() * workspace.element_size()
+            check(_lib.load().dgp_plan_create_ws(ctypes.byref(h), self.n, self.batch, self.box, self.precision,
+                                                 _ptr(workspace, None, None, "workspace"), nbytes))
         self._h = h
 
     @property
@@ -74,6 +89,7 @@ class Plan:
         if getattr(self, "_h", None) is not None:
             _lib.load().dgp_plan_destroy(self._h)
             self._h = None
+        self._ws = None   # a caller workspace may be released once the plan is gone
 
     def __enter__(self):
         return self
