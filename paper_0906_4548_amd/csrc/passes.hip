@@ -45,12 +45,18 @@ namespace dgp {
 #ifndef DGP_PLAN_P3_F32
 #define DGP_PLAN_P3_F32 0
 #endif
-// Column tile of the axis-0 passes: AxisTile, widened from N = 512 on, where the planes are
-// 2 MB (float32) or 4 MB (float64) apart and 128-byte row segments per plane stream poorly.
+// Column tile of the axis-0 passes: AxisTile, widened from N = 256 on, where the planes are
+// 0.5-4 MB apart and the narrow tile's row segments per plane stream poorly (at 256^3 the
+// float64 set-up, which also writes float32 copies, 465 -> 432 us; the float32 force mesh
+// 347 -> 331 us; a float64-form step -70 us).
+#ifndef DGP_P1_WIDE_MIN
+#define DGP_P1_WIDE_MIN 256
+#endif
 template <typename T, int N, int R>
 struct P1Tile {
   using A = AxisTile<T, N, R>;
-  static constexpr int kTP = (N >= 512 && 2 * A::kTP * A::kT <= 1024 && 2 * A::kTP <= N / 2) ? 2 * A::kTP : A::kTP;
+  static constexpr int kTP =
+      (N >= DGP_P1_WIDE_MIN && 2 * A::kTP * A::kT <= 1024 && 2 * A::kTP <= N / 2) ? 2 * A::kTP : A::kTP;
   static constexpr int kT = A::kT, kThreads = kTP * kT;
 };
 

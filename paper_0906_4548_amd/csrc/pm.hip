@@ -29,10 +29,9 @@ __device__ __forceinline__ Cic cic_at(const double (&s3)[3], int n) {
     const double s = s3[d];
     const double fl = floor(s);
     const double f = s - fl;
-    long long i = (long long)fl % n;
-    if (i < 0) i += n;
-    c.i0[d] = int(i);
-    c.i1[d] = int((i + 1) % n);
+    const int i = int((long long)fl & (n - 1));   // periodic wrap (n is a power of two)
+    c.i0[d] = i;
+    c.i1[d] = (i + 1) & (n - 1);
     c.w0[d] = 1.0 - f;
     c.w1[d] = f;
   }
@@ -54,17 +53,20 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
 // non-zero box cell to the mesh with one global atomic.  Integer sums make the result
 // identical to the direct deposit in any order; the gain needs spatially coherent
 // chunks (particles stored in compact Lagrangian blocks).  A chunk whose box is too
-// large takes the direct per-particle atomics.
-#ifndef DGP_DEPOSIT_CHUNK
-#define DGP_DEPOSIT_CHUNK 512
-#endif
-#ifndef DGP_DEPOSIT_BIN_CAP
-#define DGP_DEPOSIT_BIN_CAP 2048
-#endif
-constexpr int kDepChunk = DGP_DEPOSIT_CHUNK;   // particles per workgroup
-constexpr int kDepPPT = kDepChunk / 256;       // particles per thread
-constexpr int kBinCap = DGP_DEPOSIT_BIN_CAP;   // cells of the LDS histogram
-static_assert(kDepChunk % 256 == 0, "chunk must be a multiple of the workgroup size");
+// large takes the direct per-particle atomics.  Larger chunks mean fewer global atomics per
+// particle (a box's surface grows slower than its volume) but more registers: the chunk is
+// chosen by mesh size, from the measured deposit times of the Zel'dovich loads (256^3 float64
+// particles: 512 / 1024 / 2048 particles per chunk 357 / 299 / 322 us; 512^3 float32
+// particles: 2.84 / 2.84 / 2.45 ms).
+template <int CH>
+struct DepGeo {
+  static constexpr int kChunk = CH;            // particles per workgroup
+  static constexpr int kPPT = CH / 256;        // particles per thread
+  static constexpr int kCap = 4 * CH;          // cells of the LDS histogram (8 bytes each)
+  static_assert(CH % 256 == 0, "chunk must be a multiple of the workgroup size");
+};
+// the interpolation adjoint's scatter (up to three components per cell in LDS) keeps its own
+constexpr int kIgChunk = 512, kIgPPT = kIgChunk / 256, kIgCap = 2048;
 
 // offset of cell i from the reference cell r on a periodic axis of n cells, in [-n/2, n/2)
 __device__ __forceinline__ int periodic_offset(int i, int r, int n) {
@@ -166,25 +168,27 @@ __device__ __forceinline__ size_t box_cell(int i, const Cic& cr, const int (&bx)
   const int plane = bx[4] * bx[5];
   const int x = i / plane, r = i - x * plane;
   const int y = r / bx[5], z = r - y * bx[5];
-  const size_t gx = (size_t)(((cr.i0[0] + bx[0] + x) % n + n) % n);
-  const size_t gy = (size_t)(((cr.i0[1] + bx[1] + y) % n + n) % n);
-  const size_t gz = (size_t)(((cr.i0[2] + bx[2] + z) % n + n) % n);
+  const size_t gx = (size_t)((cr.i0[0] + bx[0] + x) & (n - 1));   // periodic wrap (n is a power of two)
+  const size_t gy = (size_t)((cr.i0[1] + bx[1] + y) & (n - 1));
+  const size_t gz = (size_t)((cr.i0[2] + bx[2] + z) & (n - 1));
   return (gx * n + gy) * n + gz;
 }
 
-template <typename P>
+template <typename P, int CH>
 __global__ void __launch_bounds__(256)
 k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsigned long long* __restrict__ grid,
               int* __restrict__ bad) {
 #pragma clang fp contract(off)
-  __shared__ unsigned long long hist[kBinCap];
-  const long long p0 = xcd_chunk() * kDepChunk;
+  using G = DepGeo<CH>;
+  constexpr int kDepPPT = G::kPPT;
+  __shared__ unsigned long long hist[G::kCap];
+  const long long p0 = xcd_chunk() * G::kChunk;
   P xs[kDepPPT][3];
   load_chunk<kDepPPT>(pos, np, p0, xs);
   flag_nonfinite<kDepPPT>(xs, bad);
   Cic cr, cs[kDepPPT];
   int off[kDepPPT][3], bx[6];
-  const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, kBinCap, cr, cs, off, bx);
+  const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, G::kCap, cr, cs, off, bx);
   const int vol = bx[3] * bx[4] * bx[5];
   if (binned)
     for (int i = threadIdx.x; i < vol; i += 256) hist[i] = 0ull;
@@ -500,23 +504,23 @@ __global__ void __launch_bounds__(256)
 k_interp_grad_mesh_bin(const P* __restrict__ pos, long long np, int n, double scale, const double* __restrict__ g,
                        const unsigned long long* __restrict__ st, unsigned long long* __restrict__ acc) {
 #pragma clang fp contract(off)
-  __shared__ unsigned long long hist[NC * kBinCap];
+  __shared__ unsigned long long hist[NC * kIgCap];
   const size_t n3 = (size_t)n * n * n;
   const int e = (int)(long long)st[2];
-  const long long p0 = xcd_chunk() * kDepChunk;
-  P xs[kDepPPT][3];
-  load_chunk<kDepPPT>(pos, np, p0, xs);
-  Cic cr, cs[kDepPPT];
-  int off[kDepPPT][3], bx[6];
-  const bool binned = chunk_box<kDepPPT>(pos, xs, np, n, scale, p0, kBinCap, cr, cs, off, bx);
+  const long long p0 = xcd_chunk() * kIgChunk;
+  P xs[kIgPPT][3];
+  load_chunk<kIgPPT>(pos, np, p0, xs);
+  Cic cr, cs[kIgPPT];
+  int off[kIgPPT][3], bx[6];
+  const bool binned = chunk_box<kIgPPT>(pos, xs, np, n, scale, p0, kIgCap, cr, cs, off, bx);
   const int vol = bx[3] * bx[4] * bx[5];
   if (binned)
     for (int i = threadIdx.x; i < vol; i += 256)
 #pragma unroll
-      for (int m = 0; m < NC; ++m) hist[m * kBinCap + i] = 0ull;
+      for (int m = 0; m < NC; ++m) hist[m * kIgCap + i] = 0ull;
   lds_barrier();
 #pragma unroll
-  for (int k = 0; k < kDepPPT; ++k) {
+  for (int k = 0; k < kIgPPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
     if (p >= np) continue;
     const Cic& c = cs[k];
@@ -537,7 +541,7 @@ k_interp_grad_mesh_bin(const P* __restrict__ pos, long long np, int n, double sc
 #pragma unroll
           for (int m = 0; m < NC; ++m) {
             const unsigned long long q = (unsigned long long)(long long)rint(ldexp(gm[m] * wgt, e));
-            if (binned) atomicAdd(&hist[m * kBinCap + li], q);
+            if (binned) atomicAdd(&hist[m * kIgCap + li], q);
             else atomicAdd(&acc[(size_t)m * n3 + gi], q);
           }
         }
@@ -550,7 +554,7 @@ k_interp_grad_mesh_bin(const P* __restrict__ pos, long long np, int n, double sc
     const size_t gi = box_cell(i, cr, bx, n);
 #pragma unroll
     for (int m = 0; m < NC; ++m) {
-      const unsigned long long v = hist[m * kBinCap + i];
+      const unsigned long long v = hist[m * kIgCap + i];
       if (v != 0ull) atomicAdd(&acc[(size_t)m * n3 + gi], v);
     }
   }
@@ -595,13 +599,19 @@ void launch_deposit(int n, double box, const void* pos, int pos_fp32, long long 
                     hipStream_t s) {
   const double scale = double(n) / box;
   auto* out = reinterpret_cast<unsigned long long*>(grid);
-  const unsigned g = unsigned((np + kDepChunk - 1) / kDepChunk);
-  if (pos_fp32)
-    hipLaunchKernelGGL((k_deposit_bin<float>), dim3(g), dim3(256), 0, s, static_cast<const float*>(pos), np, n, scale,
-                       out, bad);
+  const bool big = n >= 512;   // chunk by mesh size (DepGeo)
+  const int ch = big ? 2048 : 1024;
+  const unsigned g = unsigned((np + ch - 1) / ch);
+  const float* p32 = static_cast<const float*>(pos);
+  const double* p64 = static_cast<const double*>(pos);
+  if (pos_fp32 && big)
+    hipLaunchKernelGGL((k_deposit_bin<float, 2048>), dim3(g), dim3(256), 0, s, p32, np, n, scale, out, bad);
+  else if (pos_fp32)
+    hipLaunchKernelGGL((k_deposit_bin<float, 1024>), dim3(g), dim3(256), 0, s, p32, np, n, scale, out, bad);
+  else if (big)
+    hipLaunchKernelGGL((k_deposit_bin<double, 2048>), dim3(g), dim3(256), 0, s, p64, np, n, scale, out, bad);
   else
-    hipLaunchKernelGGL((k_deposit_bin<double>), dim3(g), dim3(256), 0, s, static_cast<const double*>(pos), np, n,
-                       scale, out, bad);
+    hipLaunchKernelGGL((k_deposit_bin<double, 1024>), dim3(g), dim3(256), 0, s, p64, np, n, scale, out, bad);
 }
 
 void launch_counts_to_delta(int n, const long long* grid, long long np, double* delta, const int* bad, hipStream_t s,
@@ -695,7 +705,7 @@ static void interp_bwd_t(int n, double box, const double* mesh, const P* pos, lo
   hipLaunchKernelGGL(k_max_abs_and_mass, dim3(grid_strided(n3)), dim3(256), 0, s, g, (size_t)NC * np, grid, n3, st,
                      bad);
   hipLaunchKernelGGL(k_interp_scale, dim3(1), dim3(64), 0, s, st);
-  const unsigned gch = unsigned((np + kDepChunk - 1) / kDepChunk);
+  const unsigned gch = unsigned((np + kIgChunk - 1) / kIgChunk);
   hipLaunchKernelGGL((k_interp_grad_mesh_bin<P, NC>), dim3(gch), dim3(256), 0, s, pos, np, n, scale, g, st, acc);
   hipLaunchKernelGGL(k_fixed_to_double, dim3(grid_strided(NC * n3)), dim3(256), 0, s, acc, NC * n3, st, bad);
 }
