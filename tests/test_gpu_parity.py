@@ -275,6 +275,32 @@ def test_deposit_binned_bit_exact(dgp, case):
         assert np.array_equal(g.cpu().numpy().reshape(n, n, n), grid_ref)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_deposit_bit_exact_512(dgp, fp32):
+    """From N = 512 the deposit takes wider chunks (2048 particles): its binned path (a compact
+    cluster wrapping the corner cell, two full chunks) and its direct fallback (a chunk mixing the
+    cluster's tail with spread particles, then a ragged chunk of spread particles) reproduce the
+    oracle's integer mesh exactly.  The meshes are compared through their non-zero cells."""
+    say("deposit 512", fp32)
+    n, box = 512, 1024.0
+    rng = np.random.default_rng(17)
+    cluster = (rng.uniform(-6.0, 6.0, (3, 5000)) + box) % box
+    spread = rng.uniform(0.0, box, (3, 3001))
+    pos = np.concatenate([cluster, spread], axis=1)
+    pos = np.ascontiguousarray(pos.astype(np.float32) if fp32 else pos)
+    ref = pm.cic_deposit_fixed(pos, n, box).reshape(-1)
+    ref_idx = np.flatnonzero(ref)
+    with dgp.Plan(n, box) as plan:
+        g = torch.zeros(n ** 3, dtype=torch.int64, device="cuda")
+        plan.deposit(to_dev(pos, torch.float32 if fp32 else torch.float64), g, None)
+        idx = torch.nonzero(g).reshape(-1)
+        vals = g[idx].cpu().numpy()
+        idx = idx.cpu().numpy()
+        del g
+    assert np.array_equal(idx, ref_idx)
+    assert np.array_equal(vals, ref[ref_idx])
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_pm_forces(dgp, mode):
     say("forces", mode)
