@@ -54,15 +54,19 @@ __device__ __forceinline__ Cic cic_of(const P* __restrict__ pos, long long np, l
 // identical to the direct deposit in any order; the gain needs spatially coherent
 // chunks (particles stored in compact Lagrangian blocks).  A chunk whose box is too
 // large takes the direct per-particle atomics.  Larger chunks mean fewer global atomics per
-// particle (a box's surface grows slower than its volume) but more registers: the chunk is
-// chosen by mesh size, from the measured deposit times of the Zel'dovich loads (256^3 float64
-// particles: 512 / 1024 / 2048 particles per chunk 357 / 299 / 322 us; 512^3 float32
-// particles: 2.84 / 2.84 / 2.45 ms).
+// particle (a box's surface grows slower than its volume) but more registers and LDS: the
+// geometry is chosen by mesh size, from the measured deposit times of the Zel'dovich loads
+// (256^3 float64 particles: 512 / 1024 / 2048 particles per chunk 357 / 299 / 322 us; 512^3
+// float32 particles: 2.84 / 2.84 / 2.45 ms).  The 2048-particle chunk recomputes each
+// particle's cell and weights after the box instead of holding them across its barriers, and
+// sizes its histogram at three cells per particle: occupancy 2 -> 3 waves per SIMD, 512^3
+// 2.43 -> 2.12 ms (the 1024-particle chunk, LDS-bound at four, gains nothing from either).
 template <int CH>
 struct DepGeo {
-  static constexpr int kChunk = CH;            // particles per workgroup
-  static constexpr int kPPT = CH / 256;        // particles per thread
-  static constexpr int kCap = 4 * CH;          // cells of the LDS histogram (8 bytes each)
+  static constexpr int kChunk = CH;                         // particles per workgroup
+  static constexpr int kPPT = CH / 256;                     // particles per thread
+  static constexpr bool kRecompute = CH >= 2048;
+  static constexpr int kCap = (kRecompute ? 3 : 4) * CH;    // cells of the LDS histogram (8 bytes each)
   static_assert(CH % 256 == 0, "chunk must be a multiple of the workgroup size");
 };
 // the interpolation adjoint's scatter (up to three components per cell in LDS) keeps its own
@@ -197,7 +201,9 @@ k_deposit_bin(const P* __restrict__ pos, long long np, int n, double scale, unsi
   for (int k = 0; k < kDepPPT; ++k) {
     const long long p = p0 + threadIdx.x + k * 256;
     if (p >= np) continue;
-    const Cic& c = cs[k];
+    // with kRecompute the cell and weights again from the position (the chunk box's arithmetic)
+    const double s3[3] = {double(xs[k][0]) * scale, double(xs[k][1]) * scale, double(xs[k][2]) * scale};
+    const Cic c = G::kRecompute ? cic_at(s3, n) : cs[k];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const double wx = a ? c.w1[0] : c.w0[0];
