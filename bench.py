@@ -485,8 +485,8 @@ def main():
         print(trace_summary(args.trace_summary))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the field solve is built for a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the field solve runs on a single MI355X "
+              "(slab sharding over several GPUs is described, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
